@@ -1,0 +1,155 @@
+/*
+ * ddhelm -- MI355X (gfx950) solver for the P1-discretised 2D Dirichlet Helmholtz
+ * problem  -Delta u - k^2 u = f  on (0,1)^2,  u = 0 on the boundary
+ * (Bootland, Dwarka, Jolivet, Dolean, Vuik, arXiv:2103.17081, Sec. 2, eqs. 1-2),
+ * by outer FGMRES (Sec. 3) preconditioned with one-level restricted additive
+ * Schwarz (Sec. 2, eq. 3) whose subdomain systems are solved inexactly by GMRES
+ * preconditioned with two-level deflation (Sec. 2, eqs. 4-5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: N intervals per edge, h = 1/N; the unknowns are the (N-1)^2 interior nodes
+ *   (i, j), 1 <= i, j <= N-1, stored x fastest: index (j-1)(N-1) + (i-1)
+ *   (the ordering Sec. 2 assumes for the Kronecker deflation matrix, eq. 5).
+ * Global vectors: interleaved complex128 (re, im), [nrhs][ndof], device memory,
+ *   contiguous, owned by the caller.
+ * Packed subdomain vectors: the tiles of all subdomains back to back, tile j at
+ *   dd_layout's fine offset, nx*ny nodes x fastest; complex128 or complex64 as the
+ *   entry point states; [nrhs][nfine] where an entry point says so.
+ * Packed coarse vectors: complex128, subdomain j at its coarse offset, mx*my values.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream); all device work
+ *   is enqueued on it.  Entry points that return host values synchronise it.
+ * Ownership: the handle owns all internal device memory (allocated by dd_setup,
+ *   freed by dd_destroy); dd_apply_preconditioner and dd_solve allocate nothing.
+ * Errors: every entry point returns a dd_status; on failure dd_last_error() gives
+ *   a message (thread-local).  Arguments are validated before any device work.
+ * Threads: a handle may be used by one host thread at a time.
+ */
+#ifndef DDHELM_H
+#define DDHELM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dd_handle dd_handle;
+
+typedef enum {
+  DD_OK = 0,
+  DD_EINVAL = 1,      /* invalid argument or unsupported configuration */
+  DD_ENOMEM = 2,      /* device allocation failed */
+  DD_EHIP = 3,        /* HIP runtime error */
+  DD_ESINGULAR = 4,   /* a coarse matrix E_j has a zero (or non-finite) pivot */
+  DD_ENOTCONV = 5,    /* outer FGMRES hit outer_maxit; the best iterate is still written */
+  DD_EWEIGHTS = 6     /* reserved: learned-guess weights rejected */
+} dd_status;
+
+enum { DD_LOCAL_IMPEDANCE = 0, DD_LOCAL_DIRICHLET = 1 };
+enum { DD_DEFLATION_LINEAR = 0, DD_DEFLATION_BEZIER = 1 };
+
+/* Problem and solver parameters.  Start from dd_default_params(). */
+typedef struct {
+  double k;            /* wave number (Sec. 2, eq. 1) */
+  double ppwl;         /* points per wavelength; used when n_intervals <= 0:
+                          N = ceil(k * ppwl / (2 pi)), so h <= 2 pi / (k ppwl) (Sec. 2) */
+  int n_intervals;     /* N > 0 overrides ppwl */
+  int px, py;          /* subdomains per direction (Cartesian partition, Sec. 2) */
+  const int* cuts_x;   /* optional host array of px+1 cut points 0 = c_0 < ... < c_px = N;
+                          NULL = uniform c_p = floor(p N / px).  Copied by dd_setup. */
+  const int* cuts_y;   /* same for y */
+  int overlap;         /* mesh-element layers appended on each interior side (>= 1; Sec. 3) */
+  int local_bc;        /* DD_LOCAL_IMPEDANCE: B_j = K_j - k^2 M_j - i k M_Gamma_j (optimised
+                          interface condition); DD_LOCAL_DIRICHLET: A_j = R_j A R_j^T (eq. 3) */
+  int deflation;       /* DD_DEFLATION_LINEAR (H = 2h interpolation); Bezier is rejected */
+  int inner_precision; /* 64: complex128 subdomain Krylov work; 32: complex64.  The coarse
+                          solve and the outer FGMRES are FP64 in both. */
+  double inner_tol;    /* relative tolerance of each subdomain GMRES on ||P_j f_j|| (Sec. 3) */
+  int inner_maxit;     /* subdomain GMRES iterations (no restart) */
+  double outer_tol;    /* FGMRES relative residual tolerance (Sec. 3: 1e-6) */
+  int outer_maxit;     /* total FGMRES iterations */
+  int outer_restart;   /* FGMRES restart length; <= 0 means outer_maxit (no restart) */
+  int nrhs;            /* independent right-hand sides solved together */
+} dd_params;
+
+typedef struct {
+  int outer_iters;             /* preconditioner applications (max over right-hand sides) */
+  int converged;               /* all right-hand sides reached outer_tol */
+  long long inner_iters_total; /* GMRES iterations over all subdomain solves */
+  long long subdomain_solves;  /* subdomain solves performed */
+  int inner_iters_max;
+  long long guesses_accepted;
+  double final_res_estimate;   /* max over rhs of the FGMRES estimate / ||f|| */
+} dd_stats;
+
+/* Fill *p with the defaults: k = 20, ppwl = 10, 2 x 2 uniform subdomains, overlap 1,
+   impedance local matrices, linear deflation, FP64 inner, inner_tol 1e-2,
+   inner_maxit 100, outer_tol 1e-6, outer_maxit 3000, no restart, nrhs 1. */
+void dd_default_params(dd_params* p);
+
+/* Build the mesh, the partition, every E_j = Z_j^T B_j Z_j (Sec. 2, eq. 4) and its
+   FP64 block LU on the device, and allocate all workspaces.  `stream` orders the
+   set-up work; the call synchronises it.  Errors: DD_EINVAL (bad parameters,
+   reported before allocating), DD_ENOMEM, DD_EHIP, DD_ESINGULAR. */
+dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out);
+
+/* z = M^{-1} r = sum_j R_j^T D_j u_j (Sec. 2, eq. 3), every u_j an inexact deflated-GMRES
+   solve of the local system with right-hand side R_j r, all subdomains and right-hand
+   sides in one launch.  r, z: device complex128 [nrhs][ndof], must not alias. */
+dd_status dd_apply_preconditioner(dd_handle* h, const void* r, void* z, void* stream);
+
+/* Solve A u = f by right-preconditioned FGMRES from u = 0 (Sec. 3).  f, u: device
+   complex128 [nrhs][ndof].  stats (host, may be NULL) receives counts.  Returns
+   DD_ENOTCONV (u still holds the last iterate) if outer_maxit is reached. */
+dd_status dd_solve(dd_handle* h, const void* f, void* u, void* stream, dd_stats* stats);
+
+dd_status dd_destroy(dd_handle* h);
+const char* dd_last_error(void);
+
+int64_t dd_num_dofs(const dd_handle* h);
+int dd_num_subdomains(const dd_handle* h);
+int dd_num_intervals(const dd_handle* h);
+/* Sizes of packed vectors: fine nodes and coarse nodes summed over subdomains. */
+int64_t dd_packed_fine_size(const dd_handle* h);
+int64_t dd_packed_coarse_size(const dd_handle* h);
+
+/* Host copy of the layout, 12 ints per subdomain (x block index fastest):
+   i0, j0, nx, ny (tile), ax, bx, ay, by (overlapping rectangle), mx, my (coarse grid),
+   fine offset, coarse offset (offsets fit in int for every supported size). */
+dd_status dd_layout(const dd_handle* h, int32_t* out);
+
+/* Host copy of the nine coefficients of E_j per coarse node (complex128, [nc][9],
+   neighbour (cx+dx, cy+dy) at 3(dy+1) + (dx+1)) and min |pivot| of its block LU. */
+dd_status dd_coarse_matrix(const dd_handle* h, int j, double* out, double* min_pivot);
+
+/* ---- kernel-level entry points (parity tests, profiling) ------------------------ */
+
+/* w = A v, global FP64 stencil (Sec. 2, eq. 2); one right-hand side. */
+dd_status dd_op_global_apply(dd_handle* h, const void* v, void* w, void* stream);
+/* w_j = B_j v_j for every subdomain; packed, complex128 (precision 64) or complex64 (32). */
+dd_status dd_op_local_apply(dd_handle* h, int precision, const void* v, void* w, void* stream);
+/* w_j = P_j B_j v_j (Sec. 2, eq. 4); packed, precision as above. */
+dd_status dd_op_deflated_apply(dd_handle* h, int precision, const void* v, void* w, void* stream);
+/* t_j = Z_j^T v_j (eq. 5, linear interpolation transpose); complex128 fine -> coarse. */
+dd_status dd_op_restrict(dd_handle* h, const void* v, void* t, void* stream);
+/* v_j = Z_j y_j; complex128 coarse -> fine. */
+dd_status dd_op_prolong(dd_handle* h, const void* y, void* v, void* stream);
+/* y_j = E_j^{-1} t_j with the FP64 block LU; complex128 coarse vectors. */
+dd_status dd_op_coarse_solve(dd_handle* h, const void* t, void* y, void* stream);
+/* f_j = R_j r (packed, precision 64 or 32) from global r; one right-hand side. */
+dd_status dd_op_gather(dd_handle* h, int precision, const void* r, void* f, void* stream);
+/* z = sum_j R_j^T D_j u_j (Boolean partition of unity) from packed u; one right-hand side. */
+dd_status dd_op_scatter(dd_handle* h, int precision, const void* u, void* z, void* stream);
+/* Batched inexact subdomain solves in the handle's inner precision: packed f [nrhs][nfine]
+   -> packed u (recovered local solutions).  guess (packed, same type) may be NULL.
+   iters and flags (host int arrays of nrhs * nsub, may be NULL) receive per-solve
+   iteration counts and flags (bit 0 guess accepted, bit 1 not converged). */
+dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void* u, int32_t* iters,
+                            int32_t* flags, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDHELM_H */

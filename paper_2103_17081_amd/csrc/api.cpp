@@ -1,0 +1,622 @@
+// C ABI of the ddhelm library: set-up of the partition and coarse factors, the
+// batched Schwarz preconditioner and the outer FGMRES driver (host side).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/ddhelm.h"
+#include "coarse.hpp"
+#include "kernels.hpp"
+#include "outer.hpp"
+
+using ddh::cplx;
+using ddh::SubDesc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dd_status fail(dd_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define DD_HIP(expr)                                                                                       \
+  do {                                                                                                      \
+    hipError_t e_ = (expr);                                                                                 \
+    if (e_ != hipSuccess)                                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP,                                          \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                                       \
+  } while (0)
+
+#define DD_TRY(expr)                  \
+  do {                                \
+    dd_status s_ = (expr);            \
+    if (s_ != DD_OK) return s_;       \
+  } while (0)
+
+constexpr int kOuterBlocks = 1024;   // workgroups of the tall-skinny outer kernels
+
+}  // namespace
+
+struct dd_handle {
+  dd_params p{};
+  int n = 0;
+  long long ndof = 0;
+  int nsub = 0, nrhs = 1, prec = 64, maxit = 0, restart = 0;
+  std::vector<int> cuts_x, cuts_y;
+  std::vector<SubDesc> subs_h;
+  long long nfine = 0, ncoarse = 0, nfac = 0;
+  int max_nj = 0, max_nc = 0;
+  ddh::Consts cs{};
+  std::vector<double> pivmin_h;
+  // device
+  SubDesc* subs = nullptr;
+  int* order = nullptr;
+  cplx<double>* Ec = nullptr;
+  cplx<double>* fac = nullptr;
+  double* pivmin = nullptr;
+  void* F = nullptr;
+  void* W = nullptr;
+  void* X = nullptr;
+  void* U = nullptr;
+  void* V = nullptr;
+  cplx<double>* R = nullptr;
+  int* iters = nullptr;
+  int* flags = nullptr;
+  unsigned long long* counters = nullptr;
+  // outer FGMRES
+  cplx<double>* Vo = nullptr;   // [nrhs][restart + 1][ndof]
+  cplx<double>* Zo = nullptr;   // [nrhs][restart][ndof]
+  cplx<double>* part = nullptr; // [nrhs][kOuterBlocks][pstride]
+  cplx<double>* coef = nullptr; // [nrhs][pstride]
+  int pstride = 0;
+  ddh::OuterState os{};
+  int* done_h = nullptr;        // pinned
+  double* res_h = nullptr;      // pinned
+  std::vector<void*> allocs;
+
+  template <typename T>
+  dd_status alloc(T** ptr, size_t count) {
+    void* q = nullptr;
+    DD_HIP(hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)));
+    allocs.push_back(q);
+    *ptr = (T*)q;
+    return DD_OK;
+  }
+  void release() {
+    for (void* q : allocs) (void)hipFree(q);
+    allocs.clear();
+    if (done_h) (void)hipHostFree(done_h);
+    if (res_h) (void)hipHostFree(res_h);
+    done_h = nullptr;
+    res_h = nullptr;
+  }
+};
+
+extern "C" {
+
+void dd_default_params(dd_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->k = 20.0;
+  p->ppwl = 10.0;
+  p->n_intervals = 0;
+  p->px = p->py = 2;
+  p->overlap = 1;
+  p->local_bc = DD_LOCAL_IMPEDANCE;
+  p->deflation = DD_DEFLATION_LINEAR;
+  p->inner_precision = 64;
+  p->inner_tol = 1e-2;
+  p->inner_maxit = 100;
+  p->outer_tol = 1e-6;
+  p->outer_maxit = 3000;
+  p->outer_restart = 0;
+  p->nrhs = 1;
+}
+
+const char* dd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+namespace {
+
+dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
+  if (!(p->k > 0.0) || !std::isfinite(p->k)) return fail(DD_EINVAL, "k must be positive and finite");
+  int n = p->n_intervals;
+  if (n <= 0) {
+    if (!(p->ppwl > 0.0)) return fail(DD_EINVAL, "ppwl must be positive when n_intervals <= 0");
+    n = (int)std::ceil(p->k * p->ppwl / (2.0 * M_PI) - 1e-9);
+  }
+  if (n < 4 || n > 65536) return fail(DD_EINVAL, "N must be in [4, 65536]");
+  if (p->px < 1 || p->py < 1 || p->px > n || p->py > n) return fail(DD_EINVAL, "bad subdomain counts");
+  if (p->overlap < 1) return fail(DD_EINVAL, "overlap must be at least one element layer");
+  if (p->local_bc != DD_LOCAL_IMPEDANCE && p->local_bc != DD_LOCAL_DIRICHLET)
+    return fail(DD_EINVAL, "local_bc must be DD_LOCAL_IMPEDANCE or DD_LOCAL_DIRICHLET");
+  if (p->deflation != DD_DEFLATION_LINEAR)
+    return fail(DD_EINVAL, "only linear deflation (H = 2h) is implemented on the GPU");
+  if (p->inner_precision != 64 && p->inner_precision != 32) return fail(DD_EINVAL, "inner_precision must be 64 or 32");
+  if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return fail(DD_EINVAL, "inner_tol must be in (0, 1)");
+  if (p->inner_maxit < 1 || p->inner_maxit > 1000) return fail(DD_EINVAL, "inner_maxit must be in [1, 1000]");
+  if (!(p->outer_tol > 0.0 && p->outer_tol < 1.0)) return fail(DD_EINVAL, "outer_tol must be in (0, 1)");
+  if (p->outer_maxit < 1) return fail(DD_EINVAL, "outer_maxit must be >= 1");
+  if (p->nrhs < 1 || p->nrhs > 64) return fail(DD_EINVAL, "nrhs must be in [1, 64]");
+  auto cuts = [&](const int* c, int parts, std::vector<int>& out) -> dd_status {
+    out.resize(parts + 1);
+    for (int q = 0; q <= parts; ++q) out[q] = c ? c[q] : (int)(((long long)q * n) / parts);
+    if (out[0] != 0 || out[parts] != n) return fail(DD_EINVAL, "cut points must start at 0 and end at N");
+    for (int q = 0; q < parts; ++q)
+      if (out[q + 1] - out[q] < 1) return fail(DD_EINVAL, "cut points must be strictly increasing");
+    return DD_OK;
+  };
+  DD_TRY(cuts(p->cuts_x, p->px, h->cuts_x));
+  DD_TRY(cuts(p->cuts_y, p->py, h->cuts_y));
+  h->p = *p;
+  h->p.cuts_x = nullptr;
+  h->p.cuts_y = nullptr;
+  h->n = n;
+  h->ndof = (long long)(n - 1) * (n - 1);
+  h->nsub = p->px * p->py;
+  h->nrhs = p->nrhs;
+  h->prec = p->inner_precision;
+  h->maxit = p->inner_maxit;
+  h->restart = p->outer_restart > 0 ? std::min(p->outer_restart, p->outer_maxit) : p->outer_maxit;
+  const int ov = p->overlap;
+  const bool imp = p->local_bc == DD_LOCAL_IMPEDANCE;
+  h->subs_h.clear();
+  long long off = 0, coff = 0, goff = 0;
+  for (int qy = 0; qy < p->py; ++qy) {
+    for (int qx = 0; qx < p->px; ++qx) {
+      SubDesc d{};
+      d.ax = std::max(0, h->cuts_x[qx] - ov);
+      d.bx = std::min(n, h->cuts_x[qx + 1] + ov);
+      d.ay = std::max(0, h->cuts_y[qy] - ov);
+      d.by = std::min(n, h->cuts_y[qy + 1] + ov);
+      int i0, i1, j0, j1;
+      if (imp) {
+        i0 = std::max(d.ax, 1); i1 = std::min(d.bx, n - 1);
+        j0 = std::max(d.ay, 1); j1 = std::min(d.by, n - 1);
+      } else {
+        i0 = d.ax + 1; i1 = d.bx - 1; j0 = d.ay + 1; j1 = d.by - 1;
+      }
+      d.i0 = i0; d.j0 = j0; d.nx = i1 - i0 + 1; d.ny = j1 - j0 + 1;
+      if (d.nx < 2 || d.ny < 2) return fail(DD_EINVAL, "every subdomain needs at least 2 x 2 local unknowns");
+      d.oi0 = std::max(h->cuts_x[qx], 1); d.oi1 = h->cuts_x[qx + 1] - 1;
+      d.oj0 = std::max(h->cuts_y[qy], 1); d.oj1 = h->cuts_y[qy + 1] - 1;
+      d.mx = d.nx / 2; d.my = d.ny / 2;
+      if (d.mx > ddh::kMaxMx) return fail(DD_EINVAL, "subdomain too wide for the coarse kernels (mx > 128)");
+      d.robin = 0;
+      if (imp) d.robin = (d.ax > 0 ? 1 : 0) | (d.bx < n ? 2 : 0) | (d.ay > 0 ? 4 : 0) | (d.by < n ? 8 : 0);
+      d.off = off; d.coff = coff; d.goff = goff;
+      off += (long long)d.nx * d.ny;
+      coff += (long long)d.mx * d.my;
+      goff += ddh::coarse_factor_size(d.mx, d.my);
+      h->max_nj = std::max(h->max_nj, d.nx * d.ny);
+      h->max_nc = std::max(h->max_nc, d.mx * d.my);
+      h->subs_h.push_back(d);
+    }
+  }
+  h->nfine = off;
+  h->ncoarse = coff;
+  h->nfac = goff;
+  h->cs.n = n;
+  h->cs.nsub = h->nsub;
+  h->cs.k = p->k;
+  h->cs.h = 1.0 / n;
+  h->cs.kh = p->k / n;
+  h->cs.kh2 = h->cs.kh * h->cs.kh;
+  return DD_OK;
+}
+
+template <typename T>
+dd_status check_lds(dd_handle* h) {
+  int dev = 0, maxlds = 0;
+  DD_HIP(hipGetDevice(&dev));
+  DD_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  size_t need = ddh::inner_lds_bytes<T>(h->max_nj, h->max_nc, h->maxit);
+  if (need > (size_t)maxlds)
+    return fail(DD_EINVAL, "subdomain tile too large for LDS (" + std::to_string(need) + " > " +
+                               std::to_string(maxlds) + " bytes); use more subdomains or fewer inner iterations");
+  return DD_OK;
+}
+
+template <typename T>
+dd_status alloc_inner(dd_handle* h) {
+  cplx<T>* q;
+  const size_t nf = (size_t)h->nfine * h->nrhs;
+  DD_TRY(h->alloc(&q, nf)); h->F = q;
+  DD_TRY(h->alloc(&q, nf)); h->W = q;
+  DD_TRY(h->alloc(&q, nf)); h->X = q;
+  DD_TRY(h->alloc(&q, nf)); h->U = q;
+  DD_TRY(h->alloc(&q, nf * (size_t)(h->maxit + 1))); h->V = q;
+  return DD_OK;
+}
+
+template <typename T>
+ddh::InnerArgs<T> inner_args(dd_handle* h) {
+  ddh::InnerArgs<T> a{};
+  a.subs = h->subs;
+  a.order = h->order;
+  a.cs = h->cs;
+  a.local_bc = h->p.local_bc;
+  a.fac = h->fac;
+  a.Ec = h->Ec;
+  a.F = (cplx<T>*)h->F;
+  a.W = (cplx<T>*)h->W;
+  a.X = (cplx<T>*)h->X;
+  a.V = (cplx<T>*)h->V;
+  a.R = h->R;
+  a.iters = h->iters;
+  a.flags = h->flags;
+  a.counters = h->counters;
+  a.nfine = h->nfine;
+  a.ndof = h->ndof;
+  a.rstride = h->ndof;
+  a.zstride = h->ndof;
+  a.nrhs = h->nrhs;
+  a.maxit = h->maxit;
+  a.max_nj = h->max_nj;
+  a.max_nc = h->max_nc;
+  a.tol = h->p.inner_tol;
+  return a;
+}
+
+// Preconditioner apply: z = M^{-1} r over all right-hand sides (those with done set are skipped).
+dd_status run_apply(dd_handle* h, const cplx<double>* r, long long rstride, cplx<double>* z, long long zstride,
+                    const int* done, hipStream_t st) {
+  if (h->prec == 32) {
+    auto a = inner_args<float>(h);
+    a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
+    DD_HIP(ddh::launch_inner_solve<float>(a, st));
+  } else {
+    auto a = inner_args<double>(h);
+    a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
+    DD_HIP(ddh::launch_inner_solve<double>(a, st));
+  }
+  return DD_OK;
+}
+
+dd_status check_handle(const dd_handle* h) {
+  if (!h) return fail(DD_EINVAL, "null handle");
+  return DD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
+  if (!p || !out) return fail(DD_EINVAL, "null argument");
+  *out = nullptr;
+  dd_handle* h = new dd_handle();
+  dd_status s = validate_and_plan(p, h);
+  if (s == DD_OK) s = h->prec == 32 ? check_lds<float>(h) : check_lds<double>(h);
+  if (s != DD_OK) {
+    delete h;
+    return s;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  auto body = [&]() -> dd_status {
+    DD_TRY(h->alloc(&h->subs, h->nsub));
+    DD_HIP(hipMemcpy(h->subs, h->subs_h.data(), h->nsub * sizeof(SubDesc), hipMemcpyHostToDevice));
+    // launch order: largest tiles first (longest-processing-time first), all right-hand sides
+    std::vector<int> ord((size_t)h->nsub * h->nrhs);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+      const SubDesc& da = h->subs_h[a % h->nsub];
+      const SubDesc& db = h->subs_h[b % h->nsub];
+      return (long long)da.nx * da.ny > (long long)db.nx * db.ny;
+    });
+    DD_TRY(h->alloc(&h->order, ord.size()));
+    DD_HIP(hipMemcpy(h->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice));
+    DD_TRY(h->alloc(&h->Ec, (size_t)h->ncoarse * 9));
+    DD_TRY(h->alloc(&h->fac, (size_t)h->nfac));
+    DD_TRY(h->alloc(&h->pivmin, h->nsub));
+    DD_HIP(ddh::launch_assemble_coarse(h->subs, h->nsub, h->cs, h->p.local_bc, h->Ec, st));
+    DD_HIP(ddh::launch_factor_coarse(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
+    h->pivmin_h.resize(h->nsub);
+    DD_HIP(hipMemcpyAsync(h->pivmin_h.data(), h->pivmin, h->nsub * sizeof(double), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < h->nsub; ++j)
+      if (!(h->pivmin_h[j] > 0.0) || !std::isfinite(h->pivmin_h[j]))
+        return fail(DD_ESINGULAR, "coarse matrix E_" + std::to_string(j) + " is singular (zero pivot)");
+    if (h->prec == 32) DD_TRY(alloc_inner<float>(h));
+    else DD_TRY(alloc_inner<double>(h));
+    DD_TRY(h->alloc(&h->R, (size_t)h->nsub * h->nrhs * h->maxit * h->maxit));
+    DD_TRY(h->alloc(&h->iters, (size_t)h->nsub * h->nrhs));
+    DD_TRY(h->alloc(&h->flags, (size_t)h->nsub * h->nrhs));
+    DD_TRY(h->alloc(&h->counters, 4));
+    // outer FGMRES workspaces
+    const int m = h->restart;
+    DD_TRY(h->alloc(&h->Vo, (size_t)h->nrhs * (m + 1) * h->ndof));
+    DD_TRY(h->alloc(&h->Zo, (size_t)h->nrhs * m * h->ndof));
+    h->pstride = std::max(m + 2, 2);
+    DD_TRY(h->alloc(&h->part, (size_t)h->nrhs * kOuterBlocks * h->pstride));
+    DD_TRY(h->alloc(&h->coef, (size_t)h->nrhs * h->pstride));
+    ddh::OuterState& o = h->os;
+    DD_TRY(h->alloc(&o.H, (size_t)h->nrhs * (m + 1)));
+    DD_TRY(h->alloc(&o.cs, (size_t)h->nrhs * m));
+    DD_TRY(h->alloc(&o.sn, (size_t)h->nrhs * m));
+    DD_TRY(h->alloc(&o.g, (size_t)h->nrhs * (m + 1)));
+    DD_TRY(h->alloc(&o.R, (size_t)h->nrhs * m * m));
+    DD_TRY(h->alloc(&o.y, (size_t)h->nrhs * m));
+    DD_TRY(h->alloc(&o.res, h->nrhs));
+    DD_TRY(h->alloc(&o.hnext, h->nrhs));
+    DD_TRY(h->alloc(&o.atol, h->nrhs));
+    DD_TRY(h->alloc(&o.steps, h->nrhs));
+    DD_TRY(h->alloc(&o.done, h->nrhs));
+    o.nrm2 = h->coef;
+    o.nrm_stride = h->pstride;
+    o.rtol = h->p.outer_tol;
+    o.restart = m;
+    DD_HIP(hipHostMalloc((void**)&h->done_h, h->nrhs * sizeof(int), hipHostMallocDefault));
+    DD_HIP(hipHostMalloc((void**)&h->res_h, h->nrhs * sizeof(double), hipHostMallocDefault));
+    return DD_OK;
+  };
+  s = body();
+  if (s != DD_OK) {
+    h->release();
+    delete h;
+    return s;
+  }
+  *out = h;
+  return DD_OK;
+}
+
+dd_status dd_destroy(dd_handle* h) {
+  if (!h) return DD_OK;
+  h->release();
+  delete h;
+  return DD_OK;
+}
+
+int64_t dd_num_dofs(const dd_handle* h) { return h ? h->ndof : 0; }
+int dd_num_subdomains(const dd_handle* h) { return h ? h->nsub : 0; }
+int dd_num_intervals(const dd_handle* h) { return h ? h->n : 0; }
+int64_t dd_packed_fine_size(const dd_handle* h) { return h ? h->nfine : 0; }
+int64_t dd_packed_coarse_size(const dd_handle* h) { return h ? h->ncoarse : 0; }
+
+dd_status dd_layout(const dd_handle* h, int32_t* out) {
+  DD_TRY(check_handle(h));
+  if (!out) return fail(DD_EINVAL, "null output");
+  for (int j = 0; j < h->nsub; ++j) {
+    const SubDesc& d = h->subs_h[j];
+    int32_t* o = out + 12 * j;
+    o[0] = d.i0; o[1] = d.j0; o[2] = d.nx; o[3] = d.ny;
+    o[4] = d.ax; o[5] = d.bx; o[6] = d.ay; o[7] = d.by;
+    o[8] = d.mx; o[9] = d.my; o[10] = (int32_t)d.off; o[11] = (int32_t)d.coff;
+  }
+  return DD_OK;
+}
+
+dd_status dd_coarse_matrix(const dd_handle* h, int j, double* out, double* min_pivot) {
+  DD_TRY(check_handle(h));
+  if (j < 0 || j >= h->nsub || !out) return fail(DD_EINVAL, "bad subdomain index or null output");
+  const SubDesc& d = h->subs_h[j];
+  DD_HIP(hipMemcpy(out, h->Ec + d.coff * 9, (size_t)d.mx * d.my * 9 * sizeof(cplx<double>), hipMemcpyDeviceToHost));
+  if (min_pivot) *min_pivot = h->pivmin_h[j];
+  return DD_OK;
+}
+
+dd_status dd_apply_preconditioner(dd_handle* h, const void* r, void* z, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!r || !z || r == z) return fail(DD_EINVAL, "r and z must be distinct non-null device pointers");
+  return run_apply(h, (const cplx<double>*)r, h->ndof, (cplx<double>*)z, h->ndof, nullptr, (hipStream_t)stream);
+}
+
+dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stats* stats) {
+  DD_TRY(check_handle(h));
+  if (!fv || !uv || fv == uv) return fail(DD_EINVAL, "f and u must be distinct non-null device pointers");
+  hipStream_t st = (hipStream_t)stream;
+  const cplx<double>* f = (const cplx<double>*)fv;
+  cplx<double>* u = (cplx<double>*)uv;
+  const int m = h->restart, nr = h->nrhs;
+  const long long nd = h->ndof;
+  const long long vstr = (long long)(m + 1) * nd, zstr = (long long)m * nd;
+  ddh::OuterState& o = h->os;
+  DD_HIP(hipMemsetAsync(h->counters, 0, 4 * sizeof(unsigned long long), st));
+  DD_HIP(hipMemsetAsync(u, 0, (size_t)nr * nd * sizeof(cplx<double>), st));
+  int total = 0;
+  bool all_done = false;
+  o.first_cycle = 1;
+  // r0 = f  (u = 0)
+  DD_HIP(hipMemcpy2DAsync(h->Vo, vstr * sizeof(cplx<double>), f, nd * sizeof(cplx<double>),
+                          nd * sizeof(cplx<double>), nr, hipMemcpyDeviceToDevice, st));
+  while (true) {
+    // ||r||, g = (beta, 0..), done flags
+    DD_HIP(ddh::launch_dots(h->Vo, vstr, h->Vo, vstr, nd, 0, 1, h->part, h->pstride, kOuterBlocks, nr, nullptr, st));
+    DD_HIP(ddh::launch_reduce_parts(h->part, kOuterBlocks, h->pstride, 1, h->coef, h->pstride, nullptr, 0, 2, nr,
+                                    nullptr, st));
+    DD_HIP(ddh::launch_cycle_init(o, nr, st));
+    DD_HIP(ddh::launch_scale(h->Vo, vstr, h->Vo, vstr, nd, o.hnext, kOuterBlocks, nr, o.done, st));
+    o.first_cycle = 0;
+    DD_HIP(hipMemcpyAsync(h->done_h, o.done, nr * sizeof(int), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    all_done = true;
+    for (int q = 0; q < nr; ++q) all_done = all_done && h->done_h[q];
+    int j = 0;
+    if (all_done) break;
+    for (; j < m && total < h->p.outer_maxit; ++j) {
+      cplx<double>* vj = h->Vo + (long long)j * nd;
+      cplx<double>* zj = h->Zo + (long long)j * nd;
+      cplx<double>* w = h->Vo + (long long)(j + 1) * nd;
+      // z_j = M^{-1} v_j (flexible: stored), w = A z_j
+      DD_TRY(run_apply(h, vj, vstr, zj, zstr, o.done, st));
+      DD_HIP(ddh::launch_global_apply_masked(h->cs, zj, zstr, w, vstr, nr, o.done, st));
+      // classical Gram-Schmidt, twice; H column accumulates both passes
+      for (int pass = 0; pass < 2; ++pass) {
+        DD_HIP(ddh::launch_dots(h->Vo, vstr, w, vstr, nd, j + 1, 0, h->part, h->pstride, kOuterBlocks, nr, o.done, st));
+        DD_HIP(ddh::launch_reduce_parts(h->part, kOuterBlocks, h->pstride, j + 1, h->coef, h->pstride, o.H, m + 1,
+                                        pass == 0 ? 0 : 1, nr, o.done, st));
+        DD_HIP(ddh::launch_update(h->Vo, vstr, w, vstr, nd, j + 1, h->coef, h->pstride, -1.0, kOuterBlocks, nr,
+                                  o.done, st));
+      }
+      DD_HIP(ddh::launch_dots(h->Vo, vstr, w, vstr, nd, 0, 1, h->part, h->pstride, kOuterBlocks, nr, o.done, st));
+      DD_HIP(ddh::launch_reduce_parts(h->part, kOuterBlocks, h->pstride, 1, h->coef, h->pstride, nullptr, 0, 2, nr,
+                                      o.done, st));
+      DD_HIP(ddh::launch_givens(o, j, nr, st));
+      DD_HIP(ddh::launch_scale(w, vstr, w, vstr, nd, o.hnext, kOuterBlocks, nr, o.done, st));
+      ++total;
+      DD_HIP(hipMemcpyAsync(h->done_h, o.done, nr * sizeof(int), hipMemcpyDeviceToHost, st));
+      DD_HIP(hipStreamSynchronize(st));
+      all_done = true;
+      for (int q = 0; q < nr; ++q) all_done = all_done && h->done_h[q];
+      if (all_done) {
+        ++j;
+        break;
+      }
+    }
+    // u += Z y
+    DD_HIP(ddh::launch_backsolve(o, nr, st));
+    DD_HIP(ddh::launch_update(h->Zo, zstr, u, nd, nd, j, o.y, m, 1.0, kOuterBlocks, nr, nullptr, st));
+    if (all_done || total >= h->p.outer_maxit) break;
+    // restart: r = f - A u
+    DD_HIP(ddh::launch_global_apply_masked(h->cs, u, nd, h->Vo, vstr, nr, nullptr, st));
+    DD_HIP(ddh::launch_residual(f, nd, h->Vo, vstr, nd, kOuterBlocks, nr, st));
+  }
+  if (stats) {
+    unsigned long long c[4];
+    DD_HIP(hipMemcpyAsync(c, h->counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipMemcpyAsync(h->res_h, o.res, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> at(nr);
+    DD_HIP(hipMemcpyAsync(at.data(), o.atol, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    stats->outer_iters = total;
+    stats->converged = all_done ? 1 : 0;
+    stats->inner_iters_total = (long long)c[0];
+    stats->subdomain_solves = (long long)c[1];
+    stats->inner_iters_max = (int)c[2];
+    stats->guesses_accepted = (long long)c[3];
+    double worst = 0.0;
+    for (int q = 0; q < nr; ++q) {
+      double rel = at[q] > 0 ? h->res_h[q] / (at[q] / h->p.outer_tol) : 0.0;
+      worst = std::max(worst, rel);
+    }
+    stats->final_res_estimate = worst;
+  }
+  return all_done ? DD_OK : fail(DD_ENOTCONV, "outer FGMRES reached outer_maxit");
+}
+
+// ---- kernel-level entry points -----------------------------------------------------
+
+dd_status dd_op_global_apply(dd_handle* h, const void* v, void* w, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!v || !w) return fail(DD_EINVAL, "null vector");
+  DD_HIP(ddh::launch_global_apply(h->cs, (const cplx<double>*)v, (cplx<double>*)w, 1, (hipStream_t)stream));
+  return DD_OK;
+}
+
+dd_status dd_op_local_apply(dd_handle* h, int precision, const void* v, void* w, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!v || !w) return fail(DD_EINVAL, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == 32)
+    DD_HIP(ddh::launch_local_apply<float>(h->subs, h->nsub, h->cs, h->p.local_bc, (const cplx<float>*)v,
+                                          (cplx<float>*)w, h->max_nj, st));
+  else if (precision == 64)
+    DD_HIP(ddh::launch_local_apply<double>(h->subs, h->nsub, h->cs, h->p.local_bc, (const cplx<double>*)v,
+                                           (cplx<double>*)w, h->max_nj, st));
+  else
+    return fail(DD_EINVAL, "precision must be 32 or 64");
+  return DD_OK;
+}
+
+dd_status dd_op_deflated_apply(dd_handle* h, int precision, const void* v, void* w, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!v || !w) return fail(DD_EINVAL, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == 32)
+    DD_HIP(ddh::launch_deflated_apply<float>(h->subs, h->nsub, h->cs, h->p.local_bc, h->fac, h->Ec,
+                                             (const cplx<float>*)v, (cplx<float>*)w, h->max_nj, h->max_nc, st));
+  else if (precision == 64)
+    DD_HIP(ddh::launch_deflated_apply<double>(h->subs, h->nsub, h->cs, h->p.local_bc, h->fac, h->Ec,
+                                              (const cplx<double>*)v, (cplx<double>*)w, h->max_nj, h->max_nc, st));
+  else
+    return fail(DD_EINVAL, "precision must be 32 or 64");
+  return DD_OK;
+}
+
+dd_status dd_op_restrict(dd_handle* h, const void* v, void* t, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!v || !t) return fail(DD_EINVAL, "null vector");
+  DD_HIP(ddh::launch_restrict(h->subs, h->nsub, (const cplx<double>*)v, (cplx<double>*)t, (hipStream_t)stream));
+  return DD_OK;
+}
+
+dd_status dd_op_prolong(dd_handle* h, const void* y, void* v, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!v || !y) return fail(DD_EINVAL, "null vector");
+  DD_HIP(ddh::launch_prolong(h->subs, h->nsub, (const cplx<double>*)y, (cplx<double>*)v, (hipStream_t)stream));
+  return DD_OK;
+}
+
+dd_status dd_op_coarse_solve(dd_handle* h, const void* t, void* y, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!t || !y || t == y) return fail(DD_EINVAL, "t and y must be distinct non-null vectors");
+  DD_HIP(ddh::launch_coarse_solve(h->subs, h->nsub, h->fac, h->Ec, (const cplx<double>*)t, (cplx<double>*)y,
+                                  h->max_nc, (hipStream_t)stream));
+  return DD_OK;
+}
+
+dd_status dd_op_gather(dd_handle* h, int precision, const void* r, void* f, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!r || !f) return fail(DD_EINVAL, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == 32)
+    DD_HIP(ddh::launch_gather<float>(h->subs, h->nsub, h->cs, (const cplx<double>*)r, (cplx<float>*)f, h->nfine,
+                                     h->ndof, 1, st));
+  else if (precision == 64)
+    DD_HIP(ddh::launch_gather<double>(h->subs, h->nsub, h->cs, (const cplx<double>*)r, (cplx<double>*)f, h->nfine,
+                                      h->ndof, 1, st));
+  else
+    return fail(DD_EINVAL, "precision must be 32 or 64");
+  return DD_OK;
+}
+
+dd_status dd_op_scatter(dd_handle* h, int precision, const void* u, void* z, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!u || !z) return fail(DD_EINVAL, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == 32)
+    DD_HIP(ddh::launch_scatter<float>(h->subs, h->nsub, h->cs, (const cplx<float>*)u, (cplx<double>*)z, h->nfine,
+                                      h->ndof, 1, st));
+  else if (precision == 64)
+    DD_HIP(ddh::launch_scatter<double>(h->subs, h->nsub, h->cs, (const cplx<double>*)u, (cplx<double>*)z,
+                                       h->nfine, h->ndof, 1, st));
+  else
+    return fail(DD_EINVAL, "precision must be 32 or 64");
+  return DD_OK;
+}
+
+dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void* u, int32_t* iters, int32_t* flags,
+                            void* stream) {
+  DD_TRY(check_handle(h));
+  if (!f || !u) return fail(DD_EINVAL, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = (size_t)h->nfine * h->nrhs * (h->prec == 32 ? 8 : 16);
+  DD_HIP(hipMemcpyAsync(h->F, f, bytes, hipMemcpyDeviceToDevice, st));
+  if (h->prec == 32) {
+    auto a = inner_args<float>(h);
+    a.guess = (const cplx<float>*)guess;
+    a.U = (cplx<float>*)u;
+    DD_HIP(ddh::launch_inner_solve<float>(a, st));
+  } else {
+    auto a = inner_args<double>(h);
+    a.guess = (const cplx<double>*)guess;
+    a.U = (cplx<double>*)u;
+    DD_HIP(ddh::launch_inner_solve<double>(a, st));
+  }
+  const size_t cnt = (size_t)h->nsub * h->nrhs;
+  if (iters) DD_HIP(hipMemcpyAsync(iters, h->iters, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (flags) DD_HIP(hipMemcpyAsync(flags, h->flags, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,611 @@
+// Batched inexact subdomain solves: GMRES on the deflated systems P_j B_j x = P_j f_j
+// (Sec. 2, eq. 4; Sec. 3), all subdomains and right-hand sides in one launch.
+//
+// One workgroup carries one (subdomain, right-hand side) pair through its whole
+// solve -- gather, deflated-operator applications, CGS2 Arnoldi with Givens
+// rotations, its own convergence test, solution recovery, scatter -- so solves of
+// uneven size and uneven iteration count run side by side without host round trips.
+// Fine-level vectors are in the template precision T; the coarse solve is FP64.
+//
+// Per solve, with f = R_j r:
+//   P f = f - B Z E^{-1} Z^T f,   reference norm ||P f||;
+//   optional guess g accepted iff ||P f - P B g|| < ||P f||, else x0 = 0;
+//   Arnoldi on w = P B v (deflated operator), classical Gram-Schmidt applied twice;
+//   stop when the least-squares residual estimate <= tol * ||P f||;
+//   x = x0 + V y,  u = x + Z E^{-1} Z^T (f - B x)   (so f - B u = P (f - B x));
+//   z(owned nodes of j) = u.
+#include "coarse.hpp"
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+namespace ddh {
+
+namespace {
+
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+template <typename T>
+struct Lds {
+  cplx<T>* A;          // fine tile (stencil input)
+  cplx<T>* B;          // fine tile (stencil output / working vector)
+  cplx<T>* tab;        // 9 row classes x 7 coefficients
+  cplx<T>* red;        // wave partial sums, kWavesPerBlock x stride
+  cplx<T>* hT;         // Gram-Schmidt coefficients of the current pass
+  cplx<double>* ct;    // coarse right-hand side
+  cplx<double>* ca;    // coarse solution
+  cplx<double>* ctmp;  // kMaxMx
+  cplx<double>* h;     // Hessenberg column (maxit + 2)
+  cplx<double>* g;     // rotated right-hand side (maxit + 1)
+  cplx<double>* sn;    // Givens sines (maxit)
+  double* cs;          // Givens cosines (maxit)
+  double* scal;        // 8 scalars
+  int* ctrl;           // 4 ints
+  int stride;          // maxit + 2
+};
+
+template <typename T>
+__host__ __device__ size_t lds_bytes(int max_nj, int max_nc, int maxit) {
+  const size_t s = (size_t)maxit + 2;
+  size_t b = 0;
+  b += 2 * align16((size_t)max_nj * sizeof(cplx<T>));
+  b += align16(kClasses * kStencilPts * sizeof(cplx<T>));
+  b += align16(kWavesPerBlock * s * sizeof(cplx<T>));
+  b += align16(s * sizeof(cplx<T>));
+  b += 2 * align16((size_t)max_nc * sizeof(cplx<double>));
+  b += align16(kMaxMx * sizeof(cplx<double>));
+  b += 4 * align16(s * sizeof(cplx<double>));
+  b += align16(s * sizeof(double));
+  b += align16(8 * sizeof(double)) + align16(4 * sizeof(int));
+  return b;
+}
+
+template <typename T>
+__device__ Lds<T> carve(unsigned char* base, int max_nj, int max_nc, int maxit) {
+  Lds<T> L;
+  const size_t s = (size_t)maxit + 2;
+  L.stride = (int)s;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { unsigned char* p = base + o; o += align16(bytes); return p; };
+  L.A = (cplx<T>*)take((size_t)max_nj * sizeof(cplx<T>));
+  L.B = (cplx<T>*)take((size_t)max_nj * sizeof(cplx<T>));
+  L.tab = (cplx<T>*)take(kClasses * kStencilPts * sizeof(cplx<T>));
+  L.red = (cplx<T>*)take(kWavesPerBlock * s * sizeof(cplx<T>));
+  L.hT = (cplx<T>*)take(s * sizeof(cplx<T>));
+  L.ct = (cplx<double>*)take((size_t)max_nc * sizeof(cplx<double>));
+  L.ca = (cplx<double>*)take((size_t)max_nc * sizeof(cplx<double>));
+  L.ctmp = (cplx<double>*)take(kMaxMx * sizeof(cplx<double>));
+  L.h = (cplx<double>*)take(s * sizeof(cplx<double>));
+  L.g = (cplx<double>*)take(s * sizeof(cplx<double>));
+  L.sn = (cplx<double>*)take(s * sizeof(cplx<double>));
+  take(s * sizeof(cplx<double>));
+  L.cs = (double*)take(s * sizeof(double));
+  L.scal = (double*)take(8 * sizeof(double));
+  L.ctrl = (int*)take(4 * sizeof(int));
+  return L;
+}
+
+// out (=|-=) B_j in over the tile; no synchronisation.
+template <typename T, bool kSubtract>
+__device__ __forceinline__ void apply_B(const SubDesc& d, const cplx<T>* tab, const cplx<T>* in, cplx<T>* out) {
+  const int nx = d.nx, ny = d.ny, nj = nx * ny;
+  for (int n = threadIdx.x; n < nj; n += blockDim.x) {
+    const int lj = n / nx, li = n - lj * nx;
+    const cplx<T>* c = tab + kStencilPts * node_class(d.i0 + li, d.j0 + lj, d.ax, d.bx, d.ay, d.by);
+    cplx<T> acc = c[kC] * in[n];
+    if (li > 0) acc = cfma(c[kW], in[n - 1], acc);
+    if (li < nx - 1) acc = cfma(c[kE], in[n + 1], acc);
+    if (lj > 0) {
+      acc = cfma(c[kS], in[n - nx], acc);
+      if (li > 0) acc = cfma(c[kSW], in[n - nx - 1], acc);
+    }
+    if (lj < ny - 1) {
+      acc = cfma(c[kN], in[n + nx], acc);
+      if (li < nx - 1) acc = cfma(c[kNE], in[n + nx + 1], acc);
+    }
+    out[n] = kSubtract ? out[n] - acc : acc;
+  }
+}
+
+// t = Z^T v (linear interpolation transpose), accumulated in double.
+template <typename T>
+__device__ __forceinline__ void restrict_to(const SubDesc& d, const cplx<T>* v, cplx<double>* t) {
+  const int nc = d.mx * d.my;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    const int cy = c / d.mx, cx = c - cy * d.mx;
+    cplx<double> acc = czero<double>();
+    for (int py = 2 * cy; py <= 2 * cy + 2 && py < d.ny; ++py) {
+      const double wy = zweight(py, cy);
+      for (int px = 2 * cx; px <= 2 * cx + 2 && px < d.nx; ++px) {
+        acc = acc + (wy * zweight(px, cx)) * ccast<double>(v[py * d.nx + px]);
+      }
+    }
+    t[c] = acc;
+  }
+}
+
+// Z y at fine node (li, lj).
+__device__ __forceinline__ cplx<double> prolong_at(const SubDesc& d, const cplx<double>* y, int li, int lj) {
+  const int ca = (li - 1) >> 1, cb = (lj - 1) >> 1;
+  cplx<double> acc = czero<double>();
+#pragma unroll
+  for (int b = cb; b <= cb + 1; ++b) {
+    if (b < 0 || b >= d.my) continue;
+    const double wy = zweight(lj, b);
+#pragma unroll
+    for (int a2 = ca; a2 <= ca + 1; ++a2) {
+      if (a2 < 0 || a2 >= d.mx) continue;
+      acc = acc + (wy * zweight(li, a2)) * y[b * d.mx + a2];
+    }
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ void prolong_to(const SubDesc& d, const cplx<double>* y, cplx<T>* v) {
+  const int nx = d.nx, nj = nx * d.ny;
+  for (int n = threadIdx.x; n < nj; n += blockDim.x) {
+    const int lj = n / nx, li = n - lj * nx;
+    v[n] = ccast<T>(prolong_at(d, y, li, lj));
+  }
+}
+
+// B := P B A  (deflated operator applied to tile A; A is overwritten).
+template <typename T>
+__device__ __forceinline__ void deflated_op(const SubDesc& d, const cplx<double>* fac, const cplx<double>* Ec,
+                                            Lds<T>& L) {
+  apply_B<T, false>(d, L.tab, L.A, L.B);
+  __syncthreads();
+  restrict_to(d, L.B, L.ct);
+  __syncthreads();
+  coarse_solve(d, fac, Ec, L.ct, L.ca, L.ctmp);
+  prolong_to(d, L.ca, L.A);
+  __syncthreads();
+  apply_B<T, true>(d, L.tab, L.A, L.B);
+  __syncthreads();
+}
+
+// Workgroup sum of a real partial; every thread gets the total.
+template <typename T>
+__device__ __forceinline__ double block_sum(T part, Lds<T>& L) {
+  part = wave_sum(part);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) L.red[wave].re = part;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWavesPerBlock; ++w) s += (double)L.red[w].re;
+  __syncthreads();
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ double tile_norm(const SubDesc& d, const cplx<T>* v, Lds<T>& L) {
+  const int nj = d.nx * d.ny;
+  T p = T(0);
+  for (int n = threadIdx.x; n < nj; n += blockDim.x) p += cabs2(v[n]);
+  return sqrt(block_sum(p, L));
+}
+
+template <typename T>
+__host__ __device__ constexpr double breakdown_eps() { return sizeof(T) == 4 ? 4e-6 : 1e-14; }
+
+}  // namespace
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int sidx = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+  const int nsub = a.cs.nsub;
+  const int rhs = sidx / nsub, sub = sidx - rhs * nsub;
+  if (a.done && a.done[rhs]) return;
+  const SubDesc d = a.subs[sub];
+  Lds<T> L = carve<T>(smem, a.max_nj, a.max_nc, a.maxit);
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int nx = d.nx, nj = d.nx * d.ny;
+  const int maxit = a.maxit;
+  const long long fo = (long long)rhs * a.nfine + d.off;
+  cplx<T>* F = a.F + fo;
+  cplx<T>* W = a.W + fo;
+  cplx<T>* X = a.X + fo;
+  cplx<T>* V = a.V + fo * (maxit + 1);
+  cplx<double>* R = a.R + (long long)sidx * maxit * maxit;
+  const int ldg = a.cs.n - 1;
+
+  build_class_table<T>(d.robin, a.cs.kh, a.cs.kh2, L.tab);
+  // gather f = R_j r into tile B (and the packed copy F)
+  for (int n = tid; n < nj; n += blockDim.x) {
+    cplx<T> v;
+    if (a.r) {
+      const int lj = n / nx, li = n - lj * nx;
+      v = ccast<T>(a.r[(long long)rhs * a.rstride + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
+      F[n] = v;
+    } else {
+      v = F[n];
+    }
+    L.B[n] = v;
+  }
+  __syncthreads();
+  // P f = f - B Z E^{-1} Z^T f   (tile B)
+  restrict_to(d, L.B, L.ct);
+  __syncthreads();
+  coarse_solve(d, a.fac, a.Ec, L.ct, L.ca, L.ctmp);
+  prolong_to(d, L.ca, L.A);
+  __syncthreads();
+  apply_B<T, true>(d, L.tab, L.A, L.B);
+  __syncthreads();
+  const double ref = tile_norm(d, L.B, L);
+
+  bool accepted = false;
+  int k = 0;
+  bool converged = true;
+  if (ref > 0.0) {
+    if (a.guess) {
+      const cplx<T>* gs = a.guess + fo;
+      for (int n = tid; n < nj; n += blockDim.x) {
+        W[n] = L.B[n];
+        const cplx<T> gv = gs[n];
+        L.A[n] = gv;
+        X[n] = gv;
+      }
+      __syncthreads();
+      deflated_op(d, a.fac, a.Ec, L);        // tile B = P B g
+      for (int n = tid; n < nj; n += blockDim.x) L.B[n] = W[n] - L.B[n];
+      __syncthreads();
+      const double rn = tile_norm(d, L.B, L);
+      accepted = rn < ref;
+      if (!accepted) {
+        for (int n = tid; n < nj; n += blockDim.x) L.B[n] = W[n];
+        __syncthreads();
+      }
+    }
+    const double beta = accepted ? tile_norm(d, L.B, L) : ref;
+    converged = beta <= a.tol * ref;
+    if (!converged) {
+      const T inv = T(1.0 / beta);
+      for (int n = tid; n < nj; n += blockDim.x) {
+        const cplx<T> v = inv * L.B[n];
+        V[n] = v;
+        L.A[n] = v;
+      }
+      if (tid == 0) L.g[0] = cplx<double>{beta, 0.0};
+      __syncthreads();
+    }
+    const int S = L.stride;
+    while (!converged && k < maxit) {
+      deflated_op(d, a.fac, a.Ec, L);       // tile B = P B v_k
+      // classical Gram-Schmidt, applied twice
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i <= k; ++i) {
+          const cplx<T>* Vi = V + (long long)i * nj;
+          cplx<T> p = czero<T>();
+          for (int n = tid; n < nj; n += blockDim.x) p = p + cmulc(Vi[n], L.B[n]);
+          p.re = wave_sum(p.re);
+          p.im = wave_sum(p.im);
+          if (lane == 0) L.red[wave * S + i] = p;
+        }
+        if (pass == 0) {
+          T q = T(0);
+          for (int n = tid; n < nj; n += blockDim.x) q += cabs2(L.B[n]);
+          q = wave_sum(q);
+          if (lane == 0) L.red[wave * S + k + 1] = cplx<T>{q, T(0)};
+        }
+        __syncthreads();
+        for (int i = tid; i <= k + (pass == 0 ? 1 : 0); i += blockDim.x) {
+          cplx<double> s = czero<double>();
+#pragma unroll
+          for (int w = 0; w < kWavesPerBlock; ++w) s = s + ccast<double>(L.red[w * S + i]);
+          if (i <= k) {
+            L.hT[i] = ccast<T>(s);
+            L.h[i] = pass == 0 ? s : L.h[i] + s;
+          } else {
+            L.scal[2] = sqrt(s.re);       // ||w|| before orthogonalisation
+          }
+        }
+        __syncthreads();
+        for (int n = tid; n < nj; n += blockDim.x) {
+          cplx<T> acc = L.B[n];
+          for (int i = 0; i <= k; ++i) acc = acc - V[(long long)i * nj + n] * L.hT[i];
+          L.B[n] = acc;
+        }
+        __syncthreads();
+      }
+      const double hnext = tile_norm(d, L.B, L);
+      if (tid == 0) {
+        cplx<double>* col = L.h;
+        for (int i = 0; i < k; ++i) {
+          const cplx<double> x0 = col[i], x1 = col[i + 1];
+          col[i] = L.cs[i] * x0 + L.sn[i] * x1;
+          col[i + 1] = L.cs[i] * x1 - cplx<double>{L.sn[i].re, -L.sn[i].im} * x0;
+        }
+        const cplx<double> av = col[k];
+        const double aa = sqrt(cabs2(av));
+        double c;
+        cplx<double> s, r;
+        if (hnext == 0.0) {
+          c = 1.0; s = czero<double>(); r = av;
+        } else if (aa == 0.0) {
+          c = 0.0; s = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
+        } else {
+          const double t = hypot(aa, hnext);
+          const cplx<double> ph = cplx<double>{av.re / aa, av.im / aa};
+          c = aa / t;
+          s = (hnext / t) * ph;
+          r = t * ph;
+        }
+        L.cs[k] = c;
+        L.sn[k] = s;
+        col[k] = r;
+        for (int i = 0; i <= k; ++i) R[(long long)k * maxit + i] = col[i];
+        const cplx<double> gk = L.g[k];
+        L.g[k + 1] = czero<double>() - cplx<double>{s.re, -s.im} * gk;
+        L.g[k] = c * gk;
+        const double res = sqrt(cabs2(L.g[k + 1]));
+        const bool brk = hnext <= breakdown_eps<T>() * L.scal[2];
+        L.ctrl[0] = (res <= a.tol * ref || brk) ? 1 : 0;
+        L.scal[1] = hnext;
+      }
+      __syncthreads();
+      converged = L.ctrl[0] != 0;
+      ++k;
+      if (!converged && k < maxit) {
+        const T inv = T(1.0 / L.scal[1]);
+        cplx<T>* Vk = V + (long long)k * nj;
+        for (int n = tid; n < nj; n += blockDim.x) {
+          const cplx<T> v = inv * L.B[n];
+          Vk[n] = v;
+          L.A[n] = v;
+        }
+        __syncthreads();
+      }
+    }
+    // y = R^{-1} g (upper triangular, k x k)
+    if (tid == 0) {
+      for (int i = k - 1; i >= 0; --i) {
+        cplx<double> s = L.g[i];
+        for (int j = i + 1; j < k; ++j) s = s - R[(long long)j * maxit + i] * L.h[j];
+        L.h[i] = s * cinv(R[(long long)i * maxit + i]);
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < k; i += blockDim.x) L.hT[i] = ccast<T>(L.h[i]);
+    __syncthreads();
+  }
+  // x = x0 + V y   (tile A)
+  for (int n = tid; n < nj; n += blockDim.x) {
+    cplx<T> x = accepted ? X[n] : czero<T>();
+    for (int i = 0; i < k; ++i) x = x + V[(long long)i * nj + n] * L.hT[i];
+    L.A[n] = x;
+  }
+  __syncthreads();
+  // recovery: u = x + Z E^{-1} Z^T (f - B x)
+  {
+    const int ny = d.ny;
+    for (int n = tid; n < nj; n += blockDim.x) {
+      const int lj = n / nx, li = n - lj * nx;
+      const cplx<T>* c = L.tab + kStencilPts * node_class(d.i0 + li, d.j0 + lj, d.ax, d.bx, d.ay, d.by);
+      cplx<T> acc = c[kC] * L.A[n];
+      if (li > 0) acc = cfma(c[kW], L.A[n - 1], acc);
+      if (li < nx - 1) acc = cfma(c[kE], L.A[n + 1], acc);
+      if (lj > 0) {
+        acc = cfma(c[kS], L.A[n - nx], acc);
+        if (li > 0) acc = cfma(c[kSW], L.A[n - nx - 1], acc);
+      }
+      if (lj < ny - 1) {
+        acc = cfma(c[kN], L.A[n + nx], acc);
+        if (li < nx - 1) acc = cfma(c[kNE], L.A[n + nx + 1], acc);
+      }
+      L.B[n] = F[n] - acc;
+    }
+  }
+  __syncthreads();
+  restrict_to(d, L.B, L.ct);
+  __syncthreads();
+  coarse_solve(d, a.fac, a.Ec, L.ct, L.ca, L.ctmp);
+  for (int n = tid; n < nj; n += blockDim.x) {
+    const int lj = n / nx, li = n - lj * nx;
+    const cplx<T> u = L.A[n] + ccast<T>(prolong_at(d, L.ca, li, lj));
+    if (a.U) a.U[fo + n] = u;
+    if (a.z) {
+      const int gi = d.i0 + li, gj = d.j0 + lj;
+      if (gi >= d.oi0 && gi <= d.oi1 && gj >= d.oj0 && gj <= d.oj1)
+        a.z[(long long)rhs * a.zstride + (long long)(gj - 1) * ldg + (gi - 1)] = ccast<double>(u);
+    }
+  }
+  if (tid == 0) {
+    if (a.iters) a.iters[sidx] = k;
+    if (a.flags) a.flags[sidx] = (accepted ? 1 : 0) | (converged ? 0 : 2);
+    if (a.counters) {
+      atomicAdd(a.counters + 0, (unsigned long long)k);
+      atomicAdd(a.counters + 1, 1ull);
+      atomicMax(a.counters + 2, (unsigned long long)k);
+      if (accepted) atomicAdd(a.counters + 3, 1ull);
+    }
+  }
+}
+
+template <typename T>
+size_t inner_lds_bytes(int max_nj, int max_nc, int maxit) {
+  return lds_bytes<T>(max_nj, max_nc, maxit);
+}
+
+template <typename T>
+hipError_t launch_inner_solve(const InnerArgs<T>& a, hipStream_t st) {
+  const size_t lds = lds_bytes<T>(a.max_nj, a.max_nc, a.maxit);
+  const int nblocks = a.cs.nsub * a.nrhs;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)inner_solve_kernel<T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(inner_solve_kernel<T>, dim3(nblocks), dim3(kBlock), lds, st, a);
+  return hipGetLastError();
+}
+
+// ---- kernel-level operations on packed vectors ---------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) local_apply_kernel(const SubDesc* __restrict__ subs, Consts cs,
+                                                              const cplx<T>* __restrict__ v,
+                                                              cplx<T>* __restrict__ w) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SubDesc d = subs[blockIdx.x];
+  cplx<T>* tab = (cplx<T>*)smem;
+  cplx<T>* tile = (cplx<T>*)(smem + align16(kClasses * kStencilPts * sizeof(cplx<T>)));
+  build_class_table<T>(d.robin, cs.kh, cs.kh2, tab);
+  const int nj = d.nx * d.ny;
+  for (int n = threadIdx.x; n < nj; n += blockDim.x) tile[n] = v[d.off + n];
+  __syncthreads();
+  apply_B<T, false>(d, tab, tile, w + d.off);
+}
+
+template <typename T>
+hipError_t launch_local_apply(const SubDesc* subs, int nsub, Consts cs, int, const cplx<T>* v, cplx<T>* w,
+                              int max_nj, hipStream_t st) {
+  const size_t lds = align16(kClasses * kStencilPts * sizeof(cplx<T>)) + (size_t)max_nj * sizeof(cplx<T>);
+  hipLaunchKernelGGL(local_apply_kernel<T>, dim3(nsub), dim3(kBlock), lds, st, subs, cs, v, w);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) deflated_apply_kernel(const SubDesc* __restrict__ subs, Consts cs,
+                                                                 const cplx<double>* __restrict__ fac,
+                                                                 const cplx<double>* __restrict__ Ec,
+                                                                 const cplx<T>* __restrict__ v,
+                                                                 cplx<T>* __restrict__ w, int max_nj, int max_nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SubDesc d = subs[blockIdx.x];
+  Lds<T> L = carve<T>(smem, max_nj, max_nc, 1);
+  build_class_table<T>(d.robin, cs.kh, cs.kh2, L.tab);
+  const int nj = d.nx * d.ny;
+  for (int n = threadIdx.x; n < nj; n += blockDim.x) L.A[n] = v[d.off + n];
+  __syncthreads();
+  deflated_op(d, fac, Ec, L);
+  for (int n = threadIdx.x; n < nj; n += blockDim.x) w[d.off + n] = L.B[n];
+}
+
+template <typename T>
+hipError_t launch_deflated_apply(const SubDesc* subs, int nsub, Consts cs, int, const cplx<double>* fac,
+                                 const cplx<double>* Ec, const cplx<T>* v, cplx<T>* w, int max_nj, int max_nc,
+                                 hipStream_t st) {
+  const size_t lds = lds_bytes<T>(max_nj, max_nc, 1);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)deflated_apply_kernel<T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(deflated_apply_kernel<T>, dim3(nsub), dim3(kBlock), lds, st, subs, cs, fac, Ec, v, w,
+                     max_nj, max_nc);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock) restrict_kernel(const SubDesc* __restrict__ subs,
+                                                           const cplx<double>* __restrict__ v,
+                                                           cplx<double>* __restrict__ t) {
+  const SubDesc d = subs[blockIdx.x];
+  restrict_to(d, v + d.off, t + d.coff);
+}
+
+hipError_t launch_restrict(const SubDesc* subs, int nsub, const cplx<double>* v, cplx<double>* t,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(restrict_kernel, dim3(nsub), dim3(kBlock), 0, st, subs, v, t);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock) prolong_kernel(const SubDesc* __restrict__ subs,
+                                                          const cplx<double>* __restrict__ y,
+                                                          cplx<double>* __restrict__ v) {
+  const SubDesc d = subs[blockIdx.x];
+  prolong_to(d, y + d.coff, v + d.off);
+}
+
+hipError_t launch_prolong(const SubDesc* subs, int nsub, const cplx<double>* y, cplx<double>* v,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(prolong_kernel, dim3(nsub), dim3(kBlock), 0, st, subs, y, v);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kBlock) coarse_solve_kernel(const SubDesc* __restrict__ subs,
+                                                               const cplx<double>* __restrict__ fac,
+                                                               const cplx<double>* __restrict__ Ec,
+                                                               const cplx<double>* __restrict__ t,
+                                                               cplx<double>* __restrict__ y, int max_nc) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SubDesc d = subs[blockIdx.x];
+  cplx<double>* ct = (cplx<double>*)smem;
+  cplx<double>* ca = ct + max_nc;
+  cplx<double>* tmp = ca + max_nc;
+  const int nc = d.mx * d.my;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) ct[c] = t[d.coff + c];
+  __syncthreads();
+  coarse_solve(d, fac, Ec, ct, ca, tmp);
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) y[d.coff + c] = ca[c];
+}
+
+hipError_t launch_coarse_solve(const SubDesc* subs, int nsub, const cplx<double>* fac, const cplx<double>* Ec,
+                               const cplx<double>* t, cplx<double>* y, int max_nc, hipStream_t st) {
+  const size_t lds = (2 * (size_t)max_nc + kMaxMx) * sizeof(cplx<double>);
+  hipLaunchKernelGGL(coarse_solve_kernel, dim3(nsub), dim3(kBlock), lds, st, subs, fac, Ec, t, y, max_nc);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) gather_kernel(const SubDesc* __restrict__ subs, Consts cs,
+                                                         const cplx<double>* __restrict__ r,
+                                                         cplx<T>* __restrict__ f, long long nfine,
+                                                         long long ndof) {
+  const SubDesc d = subs[blockIdx.x];
+  const int rhs = blockIdx.y, nj = d.nx * d.ny, ldg = cs.n - 1;
+  for (int n = threadIdx.x; n < nj; n += blockDim.x) {
+    const int lj = n / d.nx, li = n - lj * d.nx;
+    f[rhs * nfine + d.off + n] =
+        ccast<T>(r[rhs * ndof + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
+  }
+}
+
+template <typename T>
+hipError_t launch_gather(const SubDesc* subs, int nsub, Consts cs, const cplx<double>* r, cplx<T>* f,
+                         long long nfine, long long ndof, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(gather_kernel<T>, dim3(nsub, nrhs), dim3(kBlock), 0, st, subs, cs, r, f, nfine, ndof);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) scatter_kernel(const SubDesc* __restrict__ subs, Consts cs,
+                                                          const cplx<T>* __restrict__ u,
+                                                          cplx<double>* __restrict__ z, long long nfine,
+                                                          long long ndof) {
+  const SubDesc d = subs[blockIdx.x];
+  const int rhs = blockIdx.y, ldg = cs.n - 1;
+  const int ow = d.oi1 - d.oi0 + 1, oh = d.oj1 - d.oj0 + 1;
+  for (int n = threadIdx.x; n < ow * oh; n += blockDim.x) {
+    const int gj = d.oj0 + n / ow, gi = d.oi0 + n % ow;
+    const int li = gi - d.i0, lj = gj - d.j0;
+    z[rhs * ndof + (long long)(gj - 1) * ldg + (gi - 1)] = ccast<double>(u[rhs * nfine + d.off + lj * d.nx + li]);
+  }
+}
+
+template <typename T>
+hipError_t launch_scatter(const SubDesc* subs, int nsub, Consts cs, const cplx<T>* u, cplx<double>* z,
+                          long long nfine, long long ndof, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(scatter_kernel<T>, dim3(nsub, nrhs), dim3(kBlock), 0, st, subs, cs, u, z, nfine, ndof);
+  return hipGetLastError();
+}
+
+#define DDH_INSTANTIATE(T)                                                                                   \
+  template hipError_t launch_inner_solve<T>(const InnerArgs<T>&, hipStream_t);                                \
+  template size_t inner_lds_bytes<T>(int, int, int);                                                          \
+  template hipError_t launch_local_apply<T>(const SubDesc*, int, Consts, int, const cplx<T>*, cplx<T>*, int,  \
+                                            hipStream_t);                                                     \
+  template hipError_t launch_deflated_apply<T>(const SubDesc*, int, Consts, int, const cplx<double>*,         \
+                                               const cplx<double>*, const cplx<T>*, cplx<T>*, int, int,       \
+                                               hipStream_t);                                                  \
+  template hipError_t launch_gather<T>(const SubDesc*, int, Consts, const cplx<double>*, cplx<T>*, long long, \
+                                       long long, int, hipStream_t);                                          \
+  template hipError_t launch_scatter<T>(const SubDesc*, int, Consts, const cplx<T>*, cplx<double>*, long long, \
+                                        long long, int, hipStream_t);
+
+DDH_INSTANTIATE(float)
+DDH_INSTANTIATE(double)
+
+}  // namespace ddh

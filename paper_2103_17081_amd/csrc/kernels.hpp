@@ -1,0 +1,75 @@
+// Host-side launchers of the ddhelm kernels (internal to the library).
+#pragma once
+
+#include "common.hpp"
+
+namespace ddh {
+
+// ---- set-up -----------------------------------------------------------------
+hipError_t launch_assemble_coarse(const SubDesc* subs, int nsub, Consts cs, int local_bc, cplx<double>* Ec,
+                                  hipStream_t st);
+hipError_t launch_factor_coarse(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
+                                double* pivmin, hipStream_t st);
+
+// ---- subdomain solves ---------------------------------------------------------
+// Everything one batched launch of subdomain solves needs.  Packed fine vectors
+// hold the tiles of all subdomains back to back (SubDesc::off), one copy per
+// right-hand side (stride nfine).
+template <typename T>
+struct InnerArgs {
+  const SubDesc* subs;
+  const int* order;              // launch order of the solves (size nsub * nrhs), or null
+  Consts cs;
+  int local_bc;                  // 0 impedance, 1 Dirichlet
+  const cplx<double>* fac;       // coarse block-LU factors
+  const cplx<double>* Ec;        // coarse 9-point coefficients
+  const cplx<double>* r;         // global right-hand sides [nrhs][ndof], or null: use F
+  cplx<double>* z;               // global output [nrhs][ndof] (owned nodes), or null
+  cplx<T>* F;                    // packed local right-hand sides
+  cplx<T>* U;                    // packed local solutions, or null
+  const cplx<T>* guess;          // packed initial guesses, or null
+  cplx<T>* V;                    // Krylov bases: solve s at V + s_offset*(maxit+1)
+  cplx<T>* W;                    // packed work vector
+  cplx<T>* X;                    // packed work vector
+  cplx<double>* R;               // per solve maxit*maxit upper-triangular factor
+  int* iters;                    // [nrhs][nsub] inner iterations, or null
+  int* flags;                    // [nrhs][nsub] bit0 guess accepted, bit1 not converged
+  const int* done;               // [nrhs] skip right-hand sides already converged, or null
+  unsigned long long* counters;  // [4] total iterations, solves, max iterations, guesses accepted
+  long long nfine, ndof;
+  long long rstride, zstride;    // per right-hand side strides of r and z (elements)
+  int nrhs, maxit, max_nj, max_nc;
+  double tol;
+};
+
+template <typename T>
+hipError_t launch_inner_solve(const InnerArgs<T>& a, hipStream_t st);
+template <typename T>
+size_t inner_lds_bytes(int max_nj, int max_nc, int maxit);
+
+// Kernel-level operations on packed vectors (one workgroup per subdomain).
+template <typename T>
+hipError_t launch_local_apply(const SubDesc* subs, int nsub, Consts cs, int local_bc, const cplx<T>* v,
+                              cplx<T>* w, int max_nj, hipStream_t st);
+template <typename T>
+hipError_t launch_deflated_apply(const SubDesc* subs, int nsub, Consts cs, int local_bc,
+                                 const cplx<double>* fac, const cplx<double>* Ec, const cplx<T>* v,
+                                 cplx<T>* w, int max_nj, int max_nc, hipStream_t st);
+hipError_t launch_restrict(const SubDesc* subs, int nsub, const cplx<double>* v, cplx<double>* t,
+                           hipStream_t st);
+hipError_t launch_prolong(const SubDesc* subs, int nsub, const cplx<double>* y, cplx<double>* v,
+                          hipStream_t st);
+hipError_t launch_coarse_solve(const SubDesc* subs, int nsub, const cplx<double>* fac,
+                               const cplx<double>* Ec, const cplx<double>* t, cplx<double>* y, int max_nc,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_gather(const SubDesc* subs, int nsub, Consts cs, const cplx<double>* r, cplx<T>* f,
+                         long long nfine, long long ndof, int nrhs, hipStream_t st);
+template <typename T>
+hipError_t launch_scatter(const SubDesc* subs, int nsub, Consts cs, const cplx<T>* u, cplx<double>* z,
+                          long long nfine, long long ndof, int nrhs, hipStream_t st);
+
+// ---- global FP64 operations (outer FGMRES) -----------------------------------------
+hipError_t launch_global_apply(Consts cs, const cplx<double>* v, cplx<double>* w, int nrhs, hipStream_t st);
+
+}  // namespace ddh

@@ -1,0 +1,51 @@
+// Device state and launchers of the outer FP64 FGMRES.
+#pragma once
+
+#include "common.hpp"
+
+namespace ddh {
+
+constexpr int kOuterMaxDots = 64;   // Gram-Schmidt coefficients per dot-product pass chunk
+
+// Per right-hand side: Hessenberg column, rotations, rotated rhs g, R factor (restart x
+// restart, column-major), solution coefficients y, scalars.  All device pointers.
+struct OuterState {
+  cplx<double>* H;      // [nrhs][restart + 1] current column
+  double* cs;           // [nrhs][restart]
+  cplx<double>* sn;     // [nrhs][restart]
+  cplx<double>* g;      // [nrhs][restart + 1]
+  cplx<double>* R;      // [nrhs][restart][restart]
+  cplx<double>* y;      // [nrhs][restart]
+  cplx<double>* nrm2;   // norm-squared slot (read .re), stride nrm_stride
+  int nrm_stride;
+  double* res;          // [nrhs] residual estimate |g_{j+1}|
+  double* hnext;        // [nrhs]
+  double* atol;         // [nrhs] absolute tolerance rtol * ||f||
+  int* steps;           // [nrhs] columns in the current cycle
+  int* done;            // [nrhs]
+  double rtol;
+  int restart;
+  int first_cycle;
+};
+
+hipError_t launch_global_apply_masked(Consts cs, const cplx<double>* v, long long vstride, cplx<double>* w,
+                                      long long wstride, int nrhs, const int* done, hipStream_t st);
+hipError_t launch_residual(const cplx<double>* f, long long fstride, cplx<double>* w, long long wstride,
+                           long long ndof, int nblk, int nrhs, hipStream_t st);
+hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<double>* w, long long wstride,
+                       long long ndof, int nvec, int with_norm, cplx<double>* part, int pstride, int nblk,
+                       int nrhs, const int* done, hipStream_t st);
+hipError_t launch_reduce_parts(const cplx<double>* part, int nblk, int pstride, int nslots, cplx<double>* out,
+                               int ostride, cplx<double>* H, int hstride, int mode, int nrhs, const int* done,
+                               hipStream_t st);
+hipError_t launch_update(const cplx<double>* basis, long long bstride, cplx<double>* w, long long wstride,
+                         long long ndof, int nvec, const cplx<double>* coef, int cstride, double sign, int nblk,
+                         int nrhs, const int* done, hipStream_t st);
+hipError_t launch_scale(const cplx<double>* w, long long wstride, cplx<double>* out, long long ostride,
+                        long long ndof, const double* scale, int nblk, int nrhs, const int* done,
+                        hipStream_t st);
+hipError_t launch_givens(const OuterState& s, int j, int nrhs, hipStream_t st);
+hipError_t launch_backsolve(const OuterState& s, int nrhs, hipStream_t st);
+hipError_t launch_cycle_init(const OuterState& s, int nrhs, hipStream_t st);
+
+}  // namespace ddh

@@ -1,0 +1,162 @@
+// Set-up kernels: Galerkin coarse matrices E_j = Z_j^T B_j Z_j and their FP64
+// block LU (see coarse.hpp).  One workgroup per subdomain.
+#include "coarse.hpp"
+#include "kernels.hpp"
+#include "stencil.hpp"
+
+namespace ddh {
+
+// Stencil point offsets in the order of StencilPoint.
+__constant__ int kSx[kStencilPts] = {0, -1, 1, 0, 0, -1, 1};
+__constant__ int kSy[kStencilPts] = {0, 0, 0, -1, 1, -1, 1};
+
+// E(c, c+d) = sum_p Z(p, c) sum_q B(p, q) Z(q, c+d), p over the 3x3 support of Z_c.
+__global__ void __launch_bounds__(kBlock) assemble_coarse_kernel(const SubDesc* __restrict__ subs, Consts cs,
+                                                                  int local_bc, cplx<double>* __restrict__ Ec) {
+  const SubDesc d = subs[blockIdx.x];
+  __shared__ cplx<double> tab[kClasses * kStencilPts];
+  build_class_table<double>(d.robin, cs.kh, cs.kh2, tab);
+  __syncthreads();
+  const int nc = d.mx * d.my;
+  for (int e = threadIdx.x; e < nc * 9; e += blockDim.x) {
+    const int c = e / 9, o = e % 9;
+    const int cx = c % d.mx, cy = c / d.mx;
+    const int qx = cx + o % 3 - 1, qy = cy + o / 3 - 1;
+    cplx<double> acc = czero<double>();
+    if (qx >= 0 && qx < d.mx && qy >= 0 && qy < d.my) {
+      for (int py = 2 * cy; py <= 2 * cy + 2 && py < d.ny; ++py) {
+        for (int px = 2 * cx; px <= 2 * cx + 2 && px < d.nx; ++px) {
+          const double wz = zweight(px, cx) * zweight(py, cy);
+          const int cls = local_bc == 0 ? node_class(d.i0 + px, d.j0 + py, d.ax, d.bx, d.ay, d.by) : 4;
+          for (int s = 0; s < kStencilPts; ++s) {
+            const int fx = px + kSx[s], fy = py + kSy[s];
+            if (fx < 0 || fx >= d.nx || fy < 0 || fy >= d.ny) continue;
+            const double wq = zweight(fx, qx) * zweight(fy, qy);
+            if (wq != 0.0) acc = acc + (wz * wq) * tab[cls * kStencilPts + s];
+          }
+        }
+      }
+    }
+    Ec[(d.coff + c) * 9 + o] = acc;
+  }
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting of the n x n column-major
+// matrix A (global memory), workgroup-cooperative.  Returns min |pivot| (thread 0).
+__device__ double gauss_jordan_inverse(cplx<double>* A, int n, int* perm, cplx<double>* colp,
+                                       double* sh_pivabs) {
+  const int tid = threadIdx.x;
+  double minpiv = 1e300;
+  for (int p = 0; p < n; ++p) {
+    if (tid == 0) {
+      int q = p;
+      double best = cabs2(A[p * n + p]);
+      for (int r = p + 1; r < n; ++r) {
+        double v = cabs2(A[p * n + r]);
+        if (v > best) { best = v; q = r; }
+      }
+      perm[p] = q;
+      *sh_pivabs = sqrt(best);
+    }
+    __syncthreads();
+    const int q = perm[p];
+    if (q != p) {
+      for (int c = tid; c < n; c += blockDim.x) {
+        cplx<double> x = A[c * n + p];
+        A[c * n + p] = A[c * n + q];
+        A[c * n + q] = x;
+      }
+    }
+    __syncthreads();
+    const double pa = *sh_pivabs;
+    minpiv = fmin(minpiv, pa);
+    const cplx<double> inv = cinv(A[p * n + p]);
+    __syncthreads();
+    // scale row p; the pivot entry becomes 1/pivot
+    for (int c = tid; c < n; c += blockDim.x) A[c * n + p] = (c == p) ? inv : inv * A[c * n + p];
+    // stash column p before it is overwritten
+    for (int r = tid; r < n; r += blockDim.x) colp[r] = A[p * n + r];
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int r = e % n, c = e / n;
+      if (r == p) continue;
+      const cplx<double> f = colp[r];
+      A[c * n + r] = (c == p) ? czero<double>() - A[p * n + p] * f : A[c * n + r] - A[c * n + p] * f;
+    }
+    __syncthreads();
+  }
+  for (int p = n - 1; p >= 0; --p) {
+    const int q = perm[p];
+    if (q != p) {
+      for (int r = tid; r < n; r += blockDim.x) {
+        cplx<double> x = A[p * n + r];
+        A[p * n + r] = A[q * n + r];
+        A[q * n + r] = x;
+      }
+    }
+    __syncthreads();
+  }
+  return minpiv;
+}
+
+__global__ void __launch_bounds__(kBlock) factor_coarse_kernel(const SubDesc* __restrict__ subs,
+                                                                const cplx<double>* __restrict__ Ec,
+                                                                cplx<double>* __restrict__ fac,
+                                                                double* __restrict__ pivmin) {
+  const SubDesc d = subs[blockIdx.x];
+  __shared__ int perm[kMaxMx];
+  __shared__ cplx<double> colp[kMaxMx];
+  __shared__ double pivabs;
+  const int mx = d.mx, my = d.my, mm = mx * mx, tid = threadIdx.x;
+  const cplx<double>* ec = Ec + d.coff * 9;
+  cplx<double>* F = fac + d.goff;
+  double minp = 1e300;
+  for (int i = 0; i < my; ++i) {
+    cplx<double>* G = F + (size_t)i * mm;
+    const cplx<double>* Hprev = F + (size_t)(my + i - 1) * mm;
+    for (int e = tid; e < mm; e += blockDim.x) {
+      const int r = e % mx, c = e / mx;
+      const cplx<double>* row = ec + (size_t)(i * mx + r) * 9;
+      cplx<double> s = (c - r >= -1 && c - r <= 1) ? row[3 + (c - r) + 1] : czero<double>();
+      if (i > 0) {
+        for (int dr = -1; dr <= 1; ++dr) {
+          const int rr = r + dr;
+          if (rr >= 0 && rr < mx) s = s - row[dr + 1] * Hprev[c * mx + rr];
+        }
+      }
+      G[c * mx + r] = s;
+    }
+    __syncthreads();
+    minp = fmin(minp, gauss_jordan_inverse(G, mx, perm, colp, &pivabs));
+    if (i < my - 1) {
+      cplx<double>* H = F + (size_t)(my + i) * mm;
+      for (int e = tid; e < mm; e += blockDim.x) {
+        const int r = e % mx, c = e / mx;
+        cplx<double> s = czero<double>();
+        for (int dc = -1; dc <= 1; ++dc) {
+          const int cc = c + dc;    // U_i(cc, c): coupling of row-i node cc to row-(i+1) node c
+          if (cc < 0 || cc >= mx) continue;
+          const cplx<double> u = ec[(size_t)(i * mx + cc) * 9 + 6 + (c - cc) + 1];
+          s = s + G[cc * mx + r] * u;
+        }
+        H[c * mx + r] = s;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) pivmin[blockIdx.x] = minp;
+}
+
+hipError_t launch_assemble_coarse(const SubDesc* subs, int nsub, Consts cs, int local_bc, cplx<double>* Ec,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(assemble_coarse_kernel, dim3(nsub), dim3(kBlock), 0, st, subs, cs, local_bc, Ec);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_coarse(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
+                                double* pivmin, hipStream_t st) {
+  hipLaunchKernelGGL(factor_coarse_kernel, dim3(nsub), dim3(kBlock), 0, st, subs, Ec, fac, pivmin);
+  return hipGetLastError();
+}
+
+}  // namespace ddh

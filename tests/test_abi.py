@@ -1,0 +1,58 @@
+"""The C ABI without a GPU: the library loads, exports what include/ddhelm.h declares,
+fills defaults, and rejects invalid parameters on the host before any device work."""
+
+import ctypes
+import os
+
+import pytest
+
+from paper_2103_17081_amd import binding
+
+pytestmark = pytest.mark.skipif(not os.path.exists(binding.LIB_PATH),
+                                reason="libddhelm.so not built (run __graft_entry__.build())")
+
+
+def test_every_declared_symbol_is_exported():
+    names = binding.header_functions()
+    assert "dd_setup" in names and "dd_solve" in names and "dd_apply_preconditioner" in names
+    L = binding.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(binding._SIGS), "binding signatures out of sync with the header"
+
+
+def test_default_params():
+    p = binding.default_params()
+    assert p.k == 20.0 and p.ppwl == 10.0 and p.px == 2 and p.py == 2
+    assert p.overlap == 1 and p.local_bc == 0 and p.deflation == 0
+    assert p.inner_precision == 64 and p.inner_tol == 1e-2 and p.outer_tol == 1e-6
+    assert p.nrhs == 1 and p.outer_restart == 0
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(overlap=0), "overlap"),
+    (dict(k=-1.0), "k must"),
+    (dict(deflation="bezier"), "linear deflation"),
+    (dict(inner_precision=16), "inner_precision"),
+    (dict(n_intervals=32, px=2, cuts_x=[0, 16, 31]), "cut points"),
+    (dict(n_intervals=32, px=3, cuts_x=[0, 20, 20, 32]), "strictly increasing"),
+    (dict(nrhs=0), "nrhs"),
+    (dict(inner_tol=0.0), "inner_tol"),
+    (dict(outer_maxit=0), "outer_maxit"),
+    (dict(n_intervals=32, px=33), "subdomain counts"),
+    (dict(n_intervals=8, px=8, local_bc="dirichlet"), "2 x 2"),
+])
+def test_invalid_parameters_rejected_on_host(kw, needle):
+    st, msg = binding.setup_status(**kw)
+    assert st == binding.DD_EINVAL
+    assert needle in msg
+
+
+def test_null_arguments():
+    L = binding.lib()
+    assert L.dd_setup(None, None, None) == binding.DD_EINVAL
+    assert L.dd_destroy(None) == binding.DD_OK
+    assert L.dd_num_dofs(None) == 0
+    assert L.dd_apply_preconditioner(None, None, None, None) == binding.DD_EINVAL
+    assert L.dd_solve(None, None, None, None, None) == binding.DD_EINVAL
+    assert L.dd_layout(None, None) == binding.DD_EINVAL
