@@ -1,0 +1,172 @@
+#!/usr/bin/env python
+"""Benchmark of the DD-FGMRES solver on one MI355X.
+
+One step = one full solve of A u = f to outer relative residual 1e-6 (FGMRES from a
+zero guess, preconditioned by the batched inexact subdomain solves), with the
+right-hand side already resident in device memory.  The default workload is
+k = 200, 20 points per wavelength (N = 637, 404,496 unknowns), 16 x 16 subdomains
+with widths perturbed by +-25%, three seeded Gaussian sources, inner tolerance 1e-2.
+
+`value` is whole-job throughput in subdomain solves per second of the chosen form
+(complex64 subdomain Krylov work, FP64 coarse solves and outer FGMRES);
+`ms_per_step` is its time to solution.  The all-FP64 ("plain") form is timed beside
+it.  `kernels` gives, for the batched subdomain-solve kernel and the two basis sweeps
+of the outer delayed-CGS2 Arnoldi, algorithmic bytes (counted per launch by the
+library) over durations from HIP events recorded on the library's stream; `roofline`
+is the one with the largest total time.  The CPU baseline is the oracle timed on a
+bounded sample of the same workload (its first outer iterations).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DD-FGMRES time-to-solution (rel res 1e-6) & subdomain solves/s, chosen vs plain"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
+    ap.add_argument("--no-plain", action="store_true", help="skip the all-FP64 comparison solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-outer", type=int, default=40, help="outer iterations of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="before the solve, copy a 1 GiB buffer 3 times (reference kernel for HBM counters)")
+    return ap.parse_args()
+
+
+def make_solver(w, precision: int):
+    from paper_2103_17081_amd.binding import Solver
+    return Solver(w.k, n_intervals=w.n, cuts_x=w.cuts_x, cuts_y=w.cuts_y, overlap=w.overlap,
+                  inner_precision=precision, inner_tol=w.inner_tol, outer_tol=w.outer_tol,
+                  outer_maxit=4000)
+
+
+def true_relres(torch, solver, f, u):
+    r = f - solver.op_global_apply(u)
+    return float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(f))
+
+
+def timed_solves(torch, solver, f, steps: int, warmup: int):
+    for _ in range(warmup):
+        solver.solve(f)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, st = solver.solve(f)
+        stats.append(st)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, u, stats
+
+
+def cpu_baseline(w, outer: int):
+    """The oracle (complex128, scipy) on the first `outer` outer iterations of the workload."""
+    import numpy as np
+    from oracle import schwarz
+    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS")
+    S = schwarz.Schwarz(schwarz.problem_from_workload(w))
+    t0 = time.perf_counter()
+    _, st = S.solve(w.rhs[0], mode="deflated", inner_tol=w.inner_tol, outer_maxit=outer)
+    dt = time.perf_counter() - t0
+    cores = int(threads) if threads and threads.isdigit() else (os.cpu_count() or 1)
+    return {"value": st.subdomain_solves / dt, "unit": "subdomain solves/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {st.outer_iters} outer FGMRES iterations of workload '{w.name}' "
+                      f"({st.subdomain_solves} subdomain solves, avg {st.avg_inner:.1f} inner its) "
+                      f"in {dt:.1f} s; setup excluded; BLAS threads {threads or 'default'}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); multi-GPU runs are not part of "
+              "this build", file=sys.stderr)
+        return 2
+    import torch
+    from paper_2103_17081_amd import inputs
+
+    w = inputs.workload(args.workload)
+    f = torch.from_numpy(w.rhs[0]).to("cuda")
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    chosen = make_solver(w, 32)
+    t, u, stats = timed_solves(torch, chosen, f, args.steps, args.warmup)
+    last = stats[-1]
+    relres = true_relres(torch, chosen, f, u)
+    solves = sum(s["subdomain_solves"] for s in stats)
+    launches = sum(s["inner_launches"] for s in stats)
+    kernels = []
+    for name, ms_key, b_key in (("inner_solve_kernel<float, 512>", "ms_inner", "inner_bytes"),
+                                ("dots2_kernel", "ms_dots", "dots_bytes"),
+                                ("dcgs2_update_kernel", "ms_update", "update_bytes")):
+        ms = sum(s[ms_key] for s in stats)
+        by = sum(s[b_key] for s in stats)
+        ach = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        kernels.append({"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": ach / HBM_PEAK_GBS, "traffic": None, "launches": launches,
+                        "total_ms": ms, "avg_launch_ms": ms / max(launches, 1),
+                        "bytes_per_launch": by / max(launches, 1)})
+    dom = max(kernels, key=lambda k: k["total_ms"])
+    out = {
+        "metric": METRIC,
+        "value": solves / t,
+        "unit": "subdomain solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64-inner/f64-outer",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: k={w.k:g}, N={w.n} ({w.ndof} dofs), {w.nsub} subdomains "
+                               f"({len(w.cuts_x) - 1}x{len(w.cuts_y) - 1}, overlap {w.overlap}), "
+                               f"inner tol {w.inner_tol:g}, outer tol {w.outer_tol:g}, no restart",
+                   "form": "chosen (complex64 inner, FP64 coarse LU and outer FGMRES)"},
+        "chosen": {"time_to_solution_s": t / args.steps, "outer_iters": last["outer_iters"],
+                   "precond_applies": last["precond_applies"],
+                   "avg_inner_iters": last["inner_iters_total"] / max(last["subdomain_solves"], 1),
+                   "true_relres": relres, "status": last["status"],
+                   "ms_phase": {"inner": last["ms_inner"], "spmv": last["ms_spmv"],
+                                "orth": last["ms_orth"], "dots": last["ms_dots"], "update": last["ms_update"]}},
+        "roofline": dom,
+        "kernels": kernels,
+    }
+    chosen.close()
+    if not args.no_plain:
+        plain = make_solver(w, 64)
+        tp, up, sp = timed_solves(torch, plain, f, 1, 0)
+        out["plain"] = {"time_to_solution_s": tp, "outer_iters": sp[-1]["outer_iters"],
+                        "subdomain_solves_per_s": sp[-1]["subdomain_solves"] / tp,
+                        "avg_inner_iters": sp[-1]["inner_iters_total"] / max(sp[-1]["subdomain_solves"], 1),
+                        "true_relres": true_relres(torch, plain, f, up), "status": sp[-1]["status"],
+                        "ms_phase": {"inner": sp[-1]["ms_inner"], "spmv": sp[-1]["ms_spmv"],
+                                     "orth": sp[-1]["ms_orth"], "other": sp[-1]["ms_other"]}}
+        out["chosen_speedup_vs_plain"] = tp / (t / args.steps)
+        plain.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_outer)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -74,13 +74,36 @@ typedef struct {
 } dd_params;
 
 typedef struct {
-  int outer_iters;             /* preconditioner applications (max over right-hand sides) */
+  int outer_iters;             /* FGMRES columns (Krylov dimension) used, summed over restart
+                                  cycles: the count of preconditioned directions the solution needed */
+  int precond_applies;         /* preconditioner applications performed; the delayed
+                                  reorthogonalisation decides convergence one step late, so this is
+                                  outer_iters + 1 per cycle when the solve converges */
   int converged;               /* all right-hand sides reached outer_tol */
   long long inner_iters_total; /* GMRES iterations over all subdomain solves */
   long long subdomain_solves;  /* subdomain solves performed */
   int inner_iters_max;
   long long guesses_accepted;
   double final_res_estimate;   /* max over rhs of the FGMRES estimate / ||f|| */
+  /* Phase timings from HIP events recorded on `stream` around each launch group
+     (milliseconds, summed over the solve), and launch counts. */
+  double ms_inner;             /* batched subdomain-solve kernel (preconditioner) */
+  double ms_spmv;              /* global stencil A z_j */
+  double ms_orth;              /* Gram-Schmidt dot products, updates, norms */
+  double ms_other;             /* Givens, scaling, final combination */
+  int inner_launches;
+  /* Algorithmic bytes of the subdomain-solve kernel summed over its launches: per solve,
+     gather 16 n_j + scatter 16 owned_j + (k_j + 2) coarse-factor reads of
+     16 ((2 my - 1) mx^2 + 3 mx my) bytes + Krylov traffic s n_j (2 k_j + 2 k_j (k_j + 1))
+     (basis writes, CGS2 reads, final combination) + local rhs write/read 2 s n_j, with
+     s = 8 (FP32) or 16 bytes per complex value. */
+  double inner_bytes;
+  /* The two basis sweeps of the outer delayed CGS2 (events around each launch):
+     dot sweep reads the j basis vectors and two vectors, 16 nd (j + 2) bytes at step j;
+     update sweep reads the j basis vectors and two vectors and writes two,
+     16 nd (j + 4) bytes (nd unknowns, complex128). */
+  double ms_dots, ms_update;
+  double dots_bytes, update_bytes;
 } dd_stats;
 
 /* Fill *p with the defaults: k = 20, ppwl = 10, 2 x 2 uniform subdomains, overlap 1,

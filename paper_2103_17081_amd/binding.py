@@ -51,12 +51,23 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [
         ("outer_iters", ctypes.c_int),
+        ("precond_applies", ctypes.c_int),
         ("converged", ctypes.c_int),
         ("inner_iters_total", ctypes.c_longlong),
         ("subdomain_solves", ctypes.c_longlong),
         ("inner_iters_max", ctypes.c_int),
         ("guesses_accepted", ctypes.c_longlong),
         ("final_res_estimate", ctypes.c_double),
+        ("ms_inner", ctypes.c_double),
+        ("ms_spmv", ctypes.c_double),
+        ("ms_orth", ctypes.c_double),
+        ("ms_other", ctypes.c_double),
+        ("inner_launches", ctypes.c_int),
+        ("inner_bytes", ctypes.c_double),
+        ("ms_dots", ctypes.c_double),
+        ("ms_update", ctypes.c_double),
+        ("dots_bytes", ctypes.c_double),
+        ("update_bytes", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

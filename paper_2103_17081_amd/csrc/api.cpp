@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ddhelm.h"
+#include "ddhelm.h"
 #include "coarse.hpp"
 #include "kernels.hpp"
 #include "outer.hpp"
@@ -41,7 +41,8 @@ dd_status fail(dd_status s, const std::string& msg) {
     if (s_ != DD_OK) return s_;       \
   } while (0)
 
-constexpr int kOuterBlocks = 1024;   // workgroups of the tall-skinny outer kernels
+constexpr int kOuterBlocks = 1024;   // workgroups of the grid-stride outer kernels
+constexpr int kMaxRestart = 4000;    // Givens kernel stages a restart cycle in LDS
 
 }  // namespace
 
@@ -74,12 +75,17 @@ struct dd_handle {
   // outer FGMRES
   cplx<double>* Vo = nullptr;   // [nrhs][restart + 1][ndof]
   cplx<double>* Zo = nullptr;   // [nrhs][restart][ndof]
-  cplx<double>* part = nullptr; // [nrhs][kOuterBlocks][pstride]
+  cplx<double>* part = nullptr; // [nrhs][pstride][chunks]
   cplx<double>* coef = nullptr; // [nrhs][pstride]
+  cplx<double>* ca = nullptr;   // [nrhs][restart] delayed-CGS2 update coefficients
+  cplx<double>* cb = nullptr;
+  cplx<double>* scal = nullptr; // [nrhs][4]
   int pstride = 0;
   ddh::OuterState os{};
   int* done_h = nullptr;        // pinned
   double* res_h = nullptr;      // pinned
+  hipEvent_t ev[8] = {};        // phase timers of dd_solve
+  bool ev_ok = false;
   std::vector<void*> allocs;
 
   template <typename T>
@@ -93,6 +99,9 @@ struct dd_handle {
   void release() {
     for (void* q : allocs) (void)hipFree(q);
     allocs.clear();
+    if (ev_ok)
+      for (int e = 0; e < 8; ++e) (void)hipEventDestroy(ev[e]);
+    ev_ok = false;
     if (done_h) (void)hipHostFree(done_h);
     if (res_h) (void)hipHostFree(res_h);
     done_h = nullptr;
@@ -116,7 +125,7 @@ void dd_default_params(dd_params* p) {
   p->inner_tol = 1e-2;
   p->inner_maxit = 100;
   p->outer_tol = 1e-6;
-  p->outer_maxit = 3000;
+  p->outer_maxit = 3000;   /* also the restart length unless outer_restart > 0 */
   p->outer_restart = 0;
   p->nrhs = 1;
 }
@@ -167,6 +176,8 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   h->prec = p->inner_precision;
   h->maxit = p->inner_maxit;
   h->restart = p->outer_restart > 0 ? std::min(p->outer_restart, p->outer_maxit) : p->outer_maxit;
+  if (h->restart > kMaxRestart)
+    return fail(DD_EINVAL, "outer restart length (outer_maxit when outer_restart <= 0) must be <= 4000");
   const int ov = p->overlap;
   const bool imp = p->local_bc == DD_LOCAL_IMPEDANCE;
   h->subs_h.clear();
@@ -331,14 +342,19 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     DD_TRY(h->alloc(&h->R, (size_t)h->nsub * h->nrhs * h->maxit * h->maxit));
     DD_TRY(h->alloc(&h->iters, (size_t)h->nsub * h->nrhs));
     DD_TRY(h->alloc(&h->flags, (size_t)h->nsub * h->nrhs));
-    DD_TRY(h->alloc(&h->counters, 4));
+    DD_TRY(h->alloc(&h->counters, 5));
+    for (int e = 0; e < 8; ++e) DD_HIP(hipEventCreate(&h->ev[e]));
+    h->ev_ok = true;
     // outer FGMRES workspaces
     const int m = h->restart;
     DD_TRY(h->alloc(&h->Vo, (size_t)h->nrhs * (m + 1) * h->ndof));
     DD_TRY(h->alloc(&h->Zo, (size_t)h->nrhs * m * h->ndof));
-    h->pstride = std::max(m + 2, 2);
-    DD_TRY(h->alloc(&h->part, (size_t)h->nrhs * kOuterBlocks * h->pstride));
+    h->pstride = 2 * m + 4;
+    DD_TRY(h->alloc(&h->part, (size_t)h->nrhs * ddh::outer_chunks(h->ndof) * h->pstride));
     DD_TRY(h->alloc(&h->coef, (size_t)h->nrhs * h->pstride));
+    DD_TRY(h->alloc(&h->ca, (size_t)h->nrhs * m));
+    DD_TRY(h->alloc(&h->cb, (size_t)h->nrhs * m));
+    DD_TRY(h->alloc(&h->scal, (size_t)h->nrhs * 4));
     ddh::OuterState& o = h->os;
     DD_TRY(h->alloc(&o.H, (size_t)h->nrhs * (m + 1)));
     DD_TRY(h->alloc(&o.cs, (size_t)h->nrhs * m));
@@ -420,82 +436,122 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
   const long long nd = h->ndof;
   const long long vstr = (long long)(m + 1) * nd, zstr = (long long)m * nd;
   ddh::OuterState& o = h->os;
-  DD_HIP(hipMemsetAsync(h->counters, 0, 4 * sizeof(unsigned long long), st));
+  DD_HIP(hipMemsetAsync(h->counters, 0, 5 * sizeof(unsigned long long), st));
   DD_HIP(hipMemsetAsync(u, 0, (size_t)nr * nd * sizeof(cplx<double>), st));
-  int total = 0;
+  double ms[4] = {0, 0, 0, 0};
+  double ms_dots = 0, ms_upd = 0, b_dots = 0, b_upd = 0;
+  int launches = 0;
+  float el = 0.f;
+  int applies = 0, columns = 0;
   bool all_done = false;
+  std::vector<int> steps_h(nr);
   o.first_cycle = 1;
   // r0 = f  (u = 0)
   DD_HIP(hipMemcpy2DAsync(h->Vo, vstr * sizeof(cplx<double>), f, nd * sizeof(cplx<double>),
                           nd * sizeof(cplx<double>), nr, hipMemcpyDeviceToDevice, st));
-  while (true) {
-    // ||r||, g = (beta, 0..), done flags
-    DD_HIP(ddh::launch_dots(h->Vo, vstr, h->Vo, vstr, nd, 0, 1, h->part, h->pstride, kOuterBlocks, nr, nullptr, st));
-    DD_HIP(ddh::launch_reduce_parts(h->part, kOuterBlocks, h->pstride, 1, h->coef, h->pstride, nullptr, 0, 2, nr,
-                                    nullptr, st));
-    DD_HIP(ddh::launch_cycle_init(o, nr, st));
-    DD_HIP(ddh::launch_scale(h->Vo, vstr, h->Vo, vstr, nd, o.hnext, kOuterBlocks, nr, o.done, st));
-    o.first_cycle = 0;
+  auto sync_done = [&]() -> dd_status {
     DD_HIP(hipMemcpyAsync(h->done_h, o.done, nr * sizeof(int), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
     all_done = true;
     for (int q = 0; q < nr; ++q) all_done = all_done && h->done_h[q];
-    int j = 0;
+    return DD_OK;
+  };
+  while (true) {
+    // beta = ||r||, g = (beta, 0, ..), v~_0 = r / beta
+    DD_HIP(ddh::launch_dots(h->Vo, vstr, h->Vo, vstr, nd, 0, 1, h->part, h->pstride, nr, nullptr, st));
+    DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, 1, h->coef, h->pstride, nullptr, 0, 2, nr, nullptr, st));
+    DD_HIP(ddh::launch_cycle_init(o, nr, st));
+    DD_HIP(ddh::launch_scale(h->Vo, vstr, h->Vo, vstr, nd, o.hnext, kOuterBlocks, nr, o.done, st));
+    o.first_cycle = 0;
+    DD_TRY(sync_done());
     if (all_done) break;
-    for (; j < m && total < h->p.outer_maxit; ++j) {
+    int j = 0;
+    for (; j < m && applies < h->p.outer_maxit; ++j) {
       cplx<double>* vj = h->Vo + (long long)j * nd;
       cplx<double>* zj = h->Zo + (long long)j * nd;
       cplx<double>* w = h->Vo + (long long)(j + 1) * nd;
-      // z_j = M^{-1} v_j (flexible: stored), w = A z_j
+      int act = 0;          // right-hand sides active in this step
+      for (int q = 0; q < nr; ++q) act += h->done_h[q] ? 0 : 1;
+      // z_j = M^{-1} v~_j (flexible: stored), w = A z_j
+      DD_HIP(hipEventRecord(h->ev[0], st));
       DD_TRY(run_apply(h, vj, vstr, zj, zstr, o.done, st));
+      DD_HIP(hipEventRecord(h->ev[1], st));
       DD_HIP(ddh::launch_global_apply_masked(h->cs, zj, zstr, w, vstr, nr, o.done, st));
-      // classical Gram-Schmidt, twice; H column accumulates both passes
-      for (int pass = 0; pass < 2; ++pass) {
-        DD_HIP(ddh::launch_dots(h->Vo, vstr, w, vstr, nd, j + 1, 0, h->part, h->pstride, kOuterBlocks, nr, o.done, st));
-        DD_HIP(ddh::launch_reduce_parts(h->part, kOuterBlocks, h->pstride, j + 1, h->coef, h->pstride, o.H, m + 1,
-                                        pass == 0 ? 0 : 1, nr, o.done, st));
-        DD_HIP(ddh::launch_update(h->Vo, vstr, w, vstr, nd, j + 1, h->coef, h->pstride, -1.0, kOuterBlocks, nr,
-                                  o.done, st));
-      }
-      DD_HIP(ddh::launch_dots(h->Vo, vstr, w, vstr, nd, 0, 1, h->part, h->pstride, kOuterBlocks, nr, o.done, st));
-      DD_HIP(ddh::launch_reduce_parts(h->part, kOuterBlocks, h->pstride, 1, h->coef, h->pstride, nullptr, 0, 2, nr,
+      DD_HIP(hipEventRecord(h->ev[2], st));
+      // delayed CGS2: one dot sweep, bookkeeping (finalises column j-1), one update sweep
+      DD_HIP(ddh::launch_dots2(h->Vo, vstr, vj, vstr, w, vstr, nd, j, h->part, h->pstride, nr, o.done, st));
+      DD_HIP(hipEventRecord(h->ev[5], st));
+      DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, 2 * j + 3, h->coef, h->pstride, nullptr, 0, 2, nr,
                                       o.done, st));
-      DD_HIP(ddh::launch_givens(o, j, nr, st));
-      DD_HIP(ddh::launch_scale(w, vstr, w, vstr, nd, o.hnext, kOuterBlocks, nr, o.done, st));
-      ++total;
-      DD_HIP(hipMemcpyAsync(h->done_h, o.done, nr * sizeof(int), hipMemcpyDeviceToHost, st));
-      DD_HIP(hipStreamSynchronize(st));
-      all_done = true;
-      for (int q = 0; q < nr; ++q) all_done = all_done && h->done_h[q];
-      if (all_done) {
-        ++j;
-        break;
+      DD_HIP(ddh::launch_dcgs2_step(o, j, h->coef, h->pstride, 1, h->ca, h->cb, m, h->scal, nr, st));
+      DD_HIP(hipEventRecord(h->ev[6], st));
+      DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, j, h->ca, h->cb, m, h->scal, nr, o.done, st));
+      DD_HIP(hipEventRecord(h->ev[7], st));
+      DD_HIP(hipEventRecord(h->ev[3], st));
+      DD_HIP(hipEventRecord(h->ev[4], st));
+      ++applies;
+      ++launches;
+      DD_TRY(sync_done());
+      for (int e = 0; e < 4; ++e) {
+        DD_HIP(hipEventElapsedTime(&el, h->ev[e], h->ev[e + 1]));
+        ms[e] += el;
       }
+      DD_HIP(hipEventElapsedTime(&el, h->ev[2], h->ev[5]));
+      ms_dots += el;
+      DD_HIP(hipEventElapsedTime(&el, h->ev[6], h->ev[7]));
+      ms_upd += el;
+      b_dots += 16.0 * nd * (j + 2) * act;
+      b_upd += 16.0 * nd * (j + 4) * act;
+      if (all_done) break;
     }
-    // u += Z y
+    if (!all_done && j == m) {
+      // end of a cycle: finalise column m-1 from v~_m alone
+      DD_HIP(ddh::launch_dots2(h->Vo, vstr, h->Vo + (long long)m * nd, vstr, nullptr, 0, nd, m, h->part, h->pstride,
+                               nr, o.done, st));
+      DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, 2 * m + 3, h->coef, h->pstride, nullptr, 0, 2, nr,
+                                      o.done, st));
+      DD_HIP(ddh::launch_dcgs2_step(o, m, h->coef, h->pstride, 0, h->ca, h->cb, m, h->scal, nr, st));
+      DD_TRY(sync_done());
+    }
+    // u += Z y over the columns each right-hand side finalised in this cycle
     DD_HIP(ddh::launch_backsolve(o, nr, st));
-    DD_HIP(ddh::launch_update(h->Zo, zstr, u, nd, nd, j, o.y, m, 1.0, kOuterBlocks, nr, nullptr, st));
-    if (all_done || total >= h->p.outer_maxit) break;
+    DD_HIP(hipMemcpyAsync(steps_h.data(), o.steps, nr * sizeof(int), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    const int kmax = *std::max_element(steps_h.begin(), steps_h.end());
+    columns += kmax;
+    DD_HIP(ddh::launch_update(h->Zo, zstr, u, nd, nd, kmax, o.y, m, 1.0, nr, nullptr, st));
+    if (all_done || applies >= h->p.outer_maxit) break;
     // restart: r = f - A u
     DD_HIP(ddh::launch_global_apply_masked(h->cs, u, nd, h->Vo, vstr, nr, nullptr, st));
     DD_HIP(ddh::launch_residual(f, nd, h->Vo, vstr, nd, kOuterBlocks, nr, st));
   }
   if (stats) {
-    unsigned long long c[4];
+    unsigned long long c[5];
     DD_HIP(hipMemcpyAsync(c, h->counters, sizeof(c), hipMemcpyDeviceToHost, st));
     DD_HIP(hipMemcpyAsync(h->res_h, o.res, nr * sizeof(double), hipMemcpyDeviceToHost, st));
     std::vector<double> at(nr);
     DD_HIP(hipMemcpyAsync(at.data(), o.atol, nr * sizeof(double), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
-    stats->outer_iters = total;
+    stats->outer_iters = columns;
+    stats->precond_applies = applies;
     stats->converged = all_done ? 1 : 0;
     stats->inner_iters_total = (long long)c[0];
     stats->subdomain_solves = (long long)c[1];
     stats->inner_iters_max = (int)c[2];
     stats->guesses_accepted = (long long)c[3];
+    stats->inner_bytes = (double)c[4];
+    stats->ms_inner = ms[0];
+    stats->ms_spmv = ms[1];
+    stats->ms_orth = ms[2];
+    stats->ms_other = ms[3];
+    stats->inner_launches = launches;
+    stats->ms_dots = ms_dots;
+    stats->ms_update = ms_upd;
+    stats->dots_bytes = b_dots;
+    stats->update_bytes = b_upd;
     double worst = 0.0;
     for (int q = 0; q < nr; ++q) {
-      double rel = at[q] > 0 ? h->res_h[q] / (at[q] / h->p.outer_tol) : 0.0;
+      const double rel = at[q] > 0 ? h->res_h[q] / (at[q] / h->p.outer_tol) : 0.0;
       worst = std::max(worst, rel);
     }
     stats->final_res_estimate = worst;

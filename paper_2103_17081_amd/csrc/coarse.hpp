@@ -13,7 +13,7 @@
 // recurrences of a banded triangular solve; it streams the same number of bytes.
 //
 // Storage per subdomain at SubDesc::goff (complex<double>): the my blocks G_i, then
-// the my-1 blocks H_i, each mx*mx column-major (element (r, c) at c*mx + r).
+// the my-1 blocks H_i, each mx*mx row-major (element (r, c) at r*mx + c).
 // E itself is kept as nine coefficients per coarse node, offset index
 // o = 3*(dy+1) + (dx+1) for the neighbour (cx+dx, cy+dy).
 #pragma once
@@ -23,53 +23,177 @@
 namespace ddh {
 
 constexpr int kMaxMx = 128;   // largest coarse block (mx) the kernels support
+constexpr int kCoarseBatch = 8;     // block steps whose factor entries are loaded together
 
 __host__ __device__ __forceinline__ long long coarse_factor_size(int mx, int my) {
   return (long long)(2 * my - 1) * mx * mx;
 }
 
-// y = E^{-1} t for one subdomain, workgroup-cooperative.  `t` and `a` live in LDS
-// (n_c entries each, may not alias); the result overwrites `a`.  `tmp` holds mx
-// entries of LDS.  All threads of the workgroup must call it.
-__device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double>* __restrict__ fac,
-                                             const cplx<double>* __restrict__ Ec,
-                                             const cplx<double>* t, cplx<double>* a,
-                                             cplx<double>* tmp) {
-  const int mx = d.mx, my = d.my, tid = threadIdx.x;
-  const int mm = mx * mx;
+// Lanes per block row in the coarse solve: the largest power of two up to 16 with
+// lanes * mx <= NT.
+template <int NT>
+__host__ __device__ __forceinline__ int coarse_group_lanes(int mx) {
+  int l = 1;
+  while (l < 16 && 2 * l * mx <= NT) l *= 2;
+  return l;
+}
+
+// Copy the three lower couplings of every coarse node of E (neighbours (cx-1..cx+1,
+// cy-1), offsets o = 0, 1, 2) into LDS: lc[3 c + e].  Workgroup-cooperative; the
+// caller synchronises before the first coarse_solve.
+__device__ __forceinline__ void stage_lower(const SubDesc& d, const cplx<double>* __restrict__ Ec,
+                                            cplx<double>* lc) {
+  const int nc = d.mx * d.my;
   const cplx<double>* ec = Ec + d.coff * 9;
-  fac += d.goff;
-  for (int i = 0; i < my; ++i) {
-    for (int r = tid; r < mx; r += blockDim.x) {
-      cplx<double> s = t[i * mx + r];
-      if (i > 0) {
-        const cplx<double>* row = ec + (size_t)(i * mx + r) * 9;   // dy = -1: o = 0, 1, 2
+  for (int e = threadIdx.x; e < 3 * nc; e += blockDim.x) lc[e] = ec[(size_t)(e / 3) * 9 + e % 3];
+}
+
+namespace detail {
+
+// Fast path: lane l of group r owns columns c = l + q L (q < Q).  The factor entries
+// of kCoarseBatch consecutive steps are loaded together, in straight-line code with
+// clamped indices, before those steps run; memory latency is then paid once per
+// batch rather than once per step.
+template <int L, int Q>
+__device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<double>* __restrict__ F,
+                                                  const cplx<double>* lc, const cplx<double>* t,
+                                                  cplx<double>* a) {
+  const int mx = d.mx, my = d.my, mm = mx * mx;
+  const int r = threadIdx.x / L, l = threadIdx.x % L;
+  const bool active = r < mx;
+  int col[Q];
+  bool ok[Q];
 #pragma unroll
-        for (int dr = -1; dr <= 1; ++dr) {
-          int c = r + dr;
-          if (c >= 0 && c < mx) s = s - row[dr + 1] * a[(i - 1) * mx + c];
+  for (int q = 0; q < Q; ++q) {
+    col[q] = l + q * L;
+    ok[q] = active && col[q] < mx;
+  }
+  // element offset of this lane's entry q inside a block (clamped to 0 when unused)
+  int eoff[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) eoff[q] = ok[q] ? r * mx + col[q] : 0;
+  cplx<double> ring[kCoarseBatch][Q];
+  // forward: a_i = G_i (t_i - L_i a_{i-1}), G_i = block i
+  for (int i0 = 0; i0 < my; i0 += kCoarseBatch) {
+#pragma unroll
+    for (int u = 0; u < kCoarseBatch; ++u) {
+      const int blk = min(i0 + u, my - 1);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) ring[u][q] = F[(size_t)blk * mm + eoff[q]];
+    }
+#pragma unroll
+    for (int u = 0; u < kCoarseBatch; ++u) {
+      const int i = i0 + u;
+      if (i < my) {
+        cplx<double> acc = czero<double>();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int c = col[q];
+          if (ok[q]) {
+            cplx<double> rhs = t[i * mx + c];
+            if (i > 0) {
+              const cplx<double>* cpl = lc + 3 * (i * mx + c);
+              const cplx<double>* ap = a + (i - 1) * mx + c;
+              if (c > 0) rhs = rhs - cpl[0] * ap[-1];
+              rhs = rhs - cpl[1] * ap[0];
+              if (c < mx - 1) rhs = rhs - cpl[2] * ap[1];
+            }
+            acc = cfma(ring[u][q], rhs, acc);
+          }
         }
+        acc.re = row_sum<L>(acc.re);
+        acc.im = row_sum<L>(acc.im);
+        if (active && l == 0) a[i * mx + r] = acc;
+        lds_barrier();
       }
-      tmp[r] = s;
     }
-    __syncthreads();
-    const cplx<double>* G = fac + (size_t)i * mm;
-    for (int r = tid; r < mx; r += blockDim.x) {
-      cplx<double> s = czero<double>();
-      for (int c = 0; c < mx; ++c) s = cfma(G[c * mx + r], tmp[c], s);
-      a[i * mx + r] = s;
+  }
+  // backward: y_i = a_i - H_i y_{i+1}, H_i = block my + i, i = my-2 .. 0
+  for (int i0 = my - 2; i0 >= 0; i0 -= kCoarseBatch) {
+#pragma unroll
+    for (int u = 0; u < kCoarseBatch; ++u) {
+      const int blk = my + max(i0 - u, 0);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) ring[u][q] = F[(size_t)blk * mm + eoff[q]];
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kCoarseBatch; ++u) {
+      const int i = i0 - u;
+      if (i >= 0) {
+        cplx<double> acc = czero<double>();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          if (ok[q]) acc = cfma(ring[u][q], a[(i + 1) * mx + col[q]], acc);
+        acc.re = row_sum<L>(acc.re);
+        acc.im = row_sum<L>(acc.im);
+        if (active && l == 0) a[i * mx + r] = a[i * mx + r] - acc;
+        lds_barrier();
+      }
+    }
+  }
+}
+
+// General path for any mx <= kMaxMx: no prefetch, shuffle reductions.
+template <int NT>
+__device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<double>* __restrict__ F,
+                                                   const cplx<double>* lc, const cplx<double>* t,
+                                                   cplx<double>* a) {
+  const int mx = d.mx, my = d.my, mm = mx * mx;
+  const int L = coarse_group_lanes<NT>(mx);
+  const int r = threadIdx.x / L, l = threadIdx.x % L;
+  const bool active = r < mx;
+  auto gsum = [&](cplx<double> v) {
+    for (int o = L >> 1; o > 0; o >>= 1) {
+      v.re += __shfl_xor(v.re, o, kWave);
+      v.im += __shfl_xor(v.im, o, kWave);
+    }
+    return v;
+  };
+  for (int i = 0; i < my; ++i) {
+    cplx<double> acc = czero<double>();
+    if (active) {
+      for (int c = l; c < mx; c += L) {
+        cplx<double> rhs = t[i * mx + c];
+        if (i > 0) {
+          for (int e = 0; e < 3; ++e) {
+            const int cc = c + e - 1;
+            if (cc >= 0 && cc < mx) rhs = rhs - lc[3 * (i * mx + c) + e] * a[(i - 1) * mx + cc];
+          }
+        }
+        acc = cfma(F[(size_t)i * mm + r * mx + c], rhs, acc);
+      }
+    }
+    acc = gsum(acc);
+    if (active && l == 0) a[i * mx + r] = acc;
+    lds_barrier();
   }
   for (int i = my - 2; i >= 0; --i) {
-    const cplx<double>* H = fac + (size_t)(my + i) * mm;
-    for (int r = tid; r < mx; r += blockDim.x) {
-      cplx<double> s = a[i * mx + r];
-      for (int c = 0; c < mx; ++c) s = s - H[c * mx + r] * a[(i + 1) * mx + c];
-      a[i * mx + r] = s;
-    }
-    __syncthreads();
+    cplx<double> acc = czero<double>();
+    if (active)
+      for (int c = l; c < mx; c += L) acc = cfma(F[(size_t)(my + i) * mm + r * mx + c], a[(i + 1) * mx + c], acc);
+    acc = gsum(acc);
+    if (active && l == 0) a[i * mx + r] = a[i * mx + r] - acc;
+    lds_barrier();
   }
+}
+
+}  // namespace detail
+
+// y = E^{-1} t for one subdomain, workgroup-cooperative (NT threads).  `t` and `a`
+// are n_c-entry LDS arrays (must not alias); the result overwrites `a`; `lc` holds
+// the lower couplings staged by stage_lower.  `fac` is the handle's factor base (the
+// subdomain offset is applied here).  Block row r of each step is handled by a group
+// of lanes that split its columns and reduce with DPP row operations, so every step
+// costs one LDS-only barrier; factor entries are fetched a batch of steps at a time.
+template <int NT>
+__device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double>* __restrict__ fac,
+                                             const cplx<double>* lc, const cplx<double>* t, cplx<double>* a) {
+  const cplx<double>* __restrict__ F = fac + d.goff;
+  const int L = coarse_group_lanes<NT>(d.mx);
+  const int Q = (d.mx + L - 1) / L;
+  if (L == 16 && Q <= 2) detail::coarse_solve_ring<16, 2>(d, F, lc, t, a);
+  else if (L == 8 && Q <= 4) detail::coarse_solve_ring<8, 4>(d, F, lc, t, a);
+  else detail::coarse_solve_plain<NT>(d, F, lc, t, a);
 }
 
 }  // namespace ddh

@@ -11,7 +11,8 @@
 
 namespace ddh {
 
-constexpr int kBlock = 256;        // threads per workgroup of the subdomain kernels
+constexpr int kBlock = 256;        // threads per workgroup of the kernel-level subdomain operations
+constexpr int kInnerThreads = 512; // threads per workgroup of the batched subdomain-solve kernel
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kWavesPerBlock = kBlock / kWave;
 
@@ -90,7 +91,49 @@ struct Consts {
 constexpr int kStencilPts = 7;
 constexpr int kClasses = 9;        // (left edge | middle | right edge) x (bottom | middle | top)
 
+// Workgroup barrier for phases that exchange data only through LDS: waits for this
+// wave's LDS operations, not for its outstanding global loads (which __syncthreads'
+// fence would drain), so loads issued ahead of the barrier stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ---- wavefront / workgroup reductions ------------------------------------
+// DPP row operations (16-lane rows): swap adjacent lanes, swap lane pairs, mirror
+// within each half row, mirror within the row.  Applied in this order with adds,
+// every lane of a row ends with the sum over its 16 lanes (over 8 after three).
+constexpr int kDppXor1 = 0xB1;          // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;   // row_half_mirror
+constexpr int kDppMirror = 0x140;       // row_mirror
+
+template <int Ctrl>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false));
+}
+template <int Ctrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), Ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int Ctrl>
+__device__ __forceinline__ float dpp(float v) { return dpp_f32<Ctrl>(v); }
+template <int Ctrl>
+__device__ __forceinline__ double dpp(double v) { return dpp_f64<Ctrl>(v); }
+
+// Sum over each aligned group of `Lanes` (2, 4, 8 or 16) lanes; all lanes get it.
+template <int Lanes, typename T>
+__device__ __forceinline__ T row_sum(T v) {
+  static_assert(Lanes == 2 || Lanes == 4 || Lanes == 8 || Lanes == 16, "row_sum group size");
+  v += dpp<kDppXor1>(v);
+  if (Lanes >= 4) v += dpp<kDppXor2>(v);
+  if (Lanes >= 8) v += dpp<kDppHalfMirror>(v);
+  if (Lanes >= 16) v += dpp<kDppMirror>(v);
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

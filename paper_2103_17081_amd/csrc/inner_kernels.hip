@@ -33,7 +33,7 @@ struct Lds {
   cplx<T>* hT;         // Gram-Schmidt coefficients of the current pass
   cplx<double>* ct;    // coarse right-hand side
   cplx<double>* ca;    // coarse solution
-  cplx<double>* ctmp;  // kMaxMx
+  cplx<double>* lc;    // lower couplings of E staged for the coarse solve (3 per coarse node)
   cplx<double>* h;     // Hessenberg column (maxit + 2)
   cplx<double>* g;     // rotated right-hand side (maxit + 1)
   cplx<double>* sn;    // Givens sines (maxit)
@@ -44,22 +44,22 @@ struct Lds {
 };
 
 template <typename T>
-__host__ __device__ size_t lds_bytes(int max_nj, int max_nc, int maxit) {
+__host__ __device__ size_t lds_bytes(int max_nj, int max_nc, int maxit, int nt) {
   const size_t s = (size_t)maxit + 2;
   size_t b = 0;
   b += 2 * align16((size_t)max_nj * sizeof(cplx<T>));
   b += align16(kClasses * kStencilPts * sizeof(cplx<T>));
-  b += align16(kWavesPerBlock * s * sizeof(cplx<T>));
+  b += align16((size_t)(nt / kWave) * s * sizeof(cplx<T>));
   b += align16(s * sizeof(cplx<T>));
   b += 2 * align16((size_t)max_nc * sizeof(cplx<double>));
-  b += align16(kMaxMx * sizeof(cplx<double>));
-  b += 4 * align16(s * sizeof(cplx<double>));
+  b += align16((size_t)3 * max_nc * sizeof(cplx<double>));
+  b += 3 * align16(s * sizeof(cplx<double>));
   b += align16(s * sizeof(double));
   b += align16(8 * sizeof(double)) + align16(4 * sizeof(int));
   return b;
 }
 
-template <typename T>
+template <typename T, int NT>
 __device__ Lds<T> carve(unsigned char* base, int max_nj, int max_nc, int maxit) {
   Lds<T> L;
   const size_t s = (size_t)maxit + 2;
@@ -69,15 +69,14 @@ __device__ Lds<T> carve(unsigned char* base, int max_nj, int max_nc, int maxit) 
   L.A = (cplx<T>*)take((size_t)max_nj * sizeof(cplx<T>));
   L.B = (cplx<T>*)take((size_t)max_nj * sizeof(cplx<T>));
   L.tab = (cplx<T>*)take(kClasses * kStencilPts * sizeof(cplx<T>));
-  L.red = (cplx<T>*)take(kWavesPerBlock * s * sizeof(cplx<T>));
+  L.red = (cplx<T>*)take((size_t)(NT / kWave) * s * sizeof(cplx<T>));
   L.hT = (cplx<T>*)take(s * sizeof(cplx<T>));
   L.ct = (cplx<double>*)take((size_t)max_nc * sizeof(cplx<double>));
   L.ca = (cplx<double>*)take((size_t)max_nc * sizeof(cplx<double>));
-  L.ctmp = (cplx<double>*)take(kMaxMx * sizeof(cplx<double>));
+  L.lc = (cplx<double>*)take((size_t)3 * max_nc * sizeof(cplx<double>));
   L.h = (cplx<double>*)take(s * sizeof(cplx<double>));
   L.g = (cplx<double>*)take(s * sizeof(cplx<double>));
   L.sn = (cplx<double>*)take(s * sizeof(cplx<double>));
-  take(s * sizeof(cplx<double>));
   L.cs = (double*)take(s * sizeof(double));
   L.scal = (double*)take(8 * sizeof(double));
   L.ctrl = (int*)take(4 * sizeof(int));
@@ -150,41 +149,91 @@ __device__ __forceinline__ void prolong_to(const SubDesc& d, const cplx<double>*
 }
 
 // B := P B A  (deflated operator applied to tile A; A is overwritten).
-template <typename T>
-__device__ __forceinline__ void deflated_op(const SubDesc& d, const cplx<double>* fac, const cplx<double>* Ec,
-                                            Lds<T>& L) {
+template <typename T, int NT>
+__device__ __forceinline__ void deflated_op(const SubDesc& d, const cplx<double>* fac, Lds<T>& L) {
   apply_B<T, false>(d, L.tab, L.A, L.B);
-  __syncthreads();
+  lds_barrier();
   restrict_to(d, L.B, L.ct);
-  __syncthreads();
-  coarse_solve(d, fac, Ec, L.ct, L.ca, L.ctmp);
+  lds_barrier();
+  coarse_solve<NT>(d, fac, L.lc, L.ct, L.ca);
   prolong_to(d, L.ca, L.A);
-  __syncthreads();
+  lds_barrier();
   apply_B<T, true>(d, L.tab, L.A, L.B);
-  __syncthreads();
+  lds_barrier();
 }
 
 // Workgroup sum of a real partial; every thread gets the total.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ double block_sum(T part, Lds<T>& L) {
   part = wave_sum(part);
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  __syncthreads();
+  lds_barrier();
   if (lane == 0) L.red[wave].re = part;
-  __syncthreads();
+  lds_barrier();
   double s = 0.0;
 #pragma unroll
-  for (int w = 0; w < kWavesPerBlock; ++w) s += (double)L.red[w].re;
-  __syncthreads();
+  for (int w = 0; w < NT / kWave; ++w) s += (double)L.red[w].re;
+  lds_barrier();
   return s;
 }
 
-template <typename T>
+template <int NT>
+__device__ __forceinline__ double block_sum_f64(double part, double* red) {
+  part = wave_sum(part);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  lds_barrier();
+  if (lane == 0) red[wave] = part;
+  lds_barrier();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / kWave; ++w) s += red[w];
+  lds_barrier();
+  return s;
+}
+
+template <typename T, int NT>
 __device__ __forceinline__ double tile_norm(const SubDesc& d, const cplx<T>* v, Lds<T>& L) {
   const int nj = d.nx * d.ny;
   T p = T(0);
-  for (int n = threadIdx.x; n < nj; n += blockDim.x) p += cabs2(v[n]);
-  return sqrt(block_sum(p, L));
+  for (int n = threadIdx.x; n < nj; n += NT) p += cabs2(v[n]);
+  return sqrt(block_sum<T, NT>(p, L));
+}
+
+// Gram-Schmidt coefficients against V[0..k]: red[w * S + i] = wave w's partial of
+// conj(V_i) . B for i <= k, and red[w * S + k + 1] = wave w's partial of |B|^2 when
+// with_norm.  Basis vectors are swept kDotChunk at a time so that each thread keeps
+// kDotChunk independent loads per node in flight.
+constexpr int kDotChunk = 8;
+template <typename T, int NT>
+__device__ __forceinline__ void basis_dots(const cplx<T>* __restrict__ V, int nj, int k, const cplx<T>* B,
+                                           cplx<T>* red, int S, bool with_norm) {
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  for (int i0 = 0; i0 <= k; i0 += kDotChunk) {
+    cplx<T> acc[kDotChunk];
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) acc[q] = czero<T>();
+    for (int n = tid; n < nj; n += NT) {
+      const cplx<T> w = B[n];
+#pragma unroll
+      for (int q = 0; q < kDotChunk; ++q)
+        if (i0 + q <= k) acc[q] = acc[q] + cmulc(V[(long long)(i0 + q) * nj + n], w);
+    }
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) {
+      if (i0 + q <= k) {
+        cplx<T> p = acc[q];
+        p.re = wave_sum(p.re);
+        p.im = wave_sum(p.im);
+        if (lane == 0) red[wave * S + i0 + q] = p;
+      }
+    }
+  }
+  if (with_norm) {
+    T q = T(0);
+    for (int n = tid; n < nj; n += NT) q += cabs2(B[n]);
+    q = wave_sum(q);
+    if (lane == 0) red[wave * S + k + 1] = cplx<T>{q, T(0)};
+  }
 }
 
 template <typename T>
@@ -192,15 +241,15 @@ __host__ __device__ constexpr double breakdown_eps() { return sizeof(T) == 4 ? 4
 
 }  // namespace
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int sidx = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
   const int nsub = a.cs.nsub;
   const int rhs = sidx / nsub, sub = sidx - rhs * nsub;
   if (a.done && a.done[rhs]) return;
   const SubDesc d = a.subs[sub];
-  Lds<T> L = carve<T>(smem, a.max_nj, a.max_nc, a.maxit);
+  Lds<T> L = carve<T, NT>(smem, a.max_nj, a.max_nc, a.maxit);
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int nx = d.nx, nj = d.nx * d.ny;
   const int maxit = a.maxit;
@@ -213,28 +262,46 @@ __global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
   const int ldg = a.cs.n - 1;
 
   build_class_table<T>(d.robin, a.cs.kh, a.cs.kh2, L.tab);
-  // gather f = R_j r into tile B (and the packed copy F)
-  for (int n = tid; n < nj; n += blockDim.x) {
+  stage_lower(d, a.Ec, L.lc);
+  // Gather f = R_j r.  The local system is linear and its stopping test relative,
+  // so it is solved for f / ||f|| (norm taken in FP64) and the solution rescaled:
+  // local right-hand sides far from the sources are many orders of magnitude below
+  // 1 and would lose precision, or underflow, in complex64.
+  double fn2 = 0.0;
+  for (int n = tid; n < nj; n += NT) {
+    if (a.r) {
+      const int lj = n / nx, li = n - lj * nx;
+      fn2 += cabs2(a.r[(long long)rhs * a.rstride + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
+    } else {
+      fn2 += cabs2(ccast<double>(F[n]));
+    }
+  }
+  const double fnorm = sqrt(block_sum_f64<NT>(fn2, (double*)L.red));
+  const double fscale = fnorm > 0.0 ? 1.0 / fnorm : 0.0;
+  // F holds the scaled right-hand side when gathered here; a caller-supplied F is
+  // left untouched and scaled on use (fmul).
+  const T fmul = a.r ? T(1) : T(fscale);
+  for (int n = tid; n < nj; n += NT) {
     cplx<T> v;
     if (a.r) {
       const int lj = n / nx, li = n - lj * nx;
-      v = ccast<T>(a.r[(long long)rhs * a.rstride + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
+      v = ccast<T>(fscale * a.r[(long long)rhs * a.rstride + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
       F[n] = v;
     } else {
-      v = F[n];
+      v = fmul * F[n];
     }
     L.B[n] = v;
   }
-  __syncthreads();
+  lds_barrier();
   // P f = f - B Z E^{-1} Z^T f   (tile B)
   restrict_to(d, L.B, L.ct);
-  __syncthreads();
-  coarse_solve(d, a.fac, a.Ec, L.ct, L.ca, L.ctmp);
+  lds_barrier();
+  coarse_solve<NT>(d, a.fac, L.lc, L.ct, L.ca);
   prolong_to(d, L.ca, L.A);
-  __syncthreads();
+  lds_barrier();
   apply_B<T, true>(d, L.tab, L.A, L.B);
-  __syncthreads();
-  const double ref = tile_norm(d, L.B, L);
+  lds_barrier();
+  const double ref = tile_norm<T, NT>(d, L.B, L);
 
   bool accepted = false;
   int k = 0;
@@ -242,28 +309,29 @@ __global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
   if (ref > 0.0) {
     if (a.guess) {
       const cplx<T>* gs = a.guess + fo;
-      for (int n = tid; n < nj; n += blockDim.x) {
+      const T gmul = T(fscale);
+      for (int n = tid; n < nj; n += NT) {
         W[n] = L.B[n];
-        const cplx<T> gv = gs[n];
+        const cplx<T> gv = gmul * gs[n];
         L.A[n] = gv;
         X[n] = gv;
       }
-      __syncthreads();
-      deflated_op(d, a.fac, a.Ec, L);        // tile B = P B g
-      for (int n = tid; n < nj; n += blockDim.x) L.B[n] = W[n] - L.B[n];
-      __syncthreads();
-      const double rn = tile_norm(d, L.B, L);
+      lds_barrier();
+      deflated_op<T, NT>(d, a.fac, L);   // tile B = P B g
+      for (int n = tid; n < nj; n += NT) L.B[n] = W[n] - L.B[n];
+      lds_barrier();
+      const double rn = tile_norm<T, NT>(d, L.B, L);
       accepted = rn < ref;
       if (!accepted) {
-        for (int n = tid; n < nj; n += blockDim.x) L.B[n] = W[n];
-        __syncthreads();
+        for (int n = tid; n < nj; n += NT) L.B[n] = W[n];
+        lds_barrier();
       }
     }
-    const double beta = accepted ? tile_norm(d, L.B, L) : ref;
+    const double beta = accepted ? tile_norm<T, NT>(d, L.B, L) : ref;
     converged = beta <= a.tol * ref;
     if (!converged) {
       const T inv = T(1.0 / beta);
-      for (int n = tid; n < nj; n += blockDim.x) {
+      for (int n = tid; n < nj; n += NT) {
         const cplx<T> v = inv * L.B[n];
         V[n] = v;
         L.A[n] = v;
@@ -273,44 +341,31 @@ __global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
     }
     const int S = L.stride;
     while (!converged && k < maxit) {
-      deflated_op(d, a.fac, a.Ec, L);       // tile B = P B v_k
+      deflated_op<T, NT>(d, a.fac, L);   // tile B = P B v_k
       // classical Gram-Schmidt, applied twice
       for (int pass = 0; pass < 2; ++pass) {
-        for (int i = 0; i <= k; ++i) {
-          const cplx<T>* Vi = V + (long long)i * nj;
-          cplx<T> p = czero<T>();
-          for (int n = tid; n < nj; n += blockDim.x) p = p + cmulc(Vi[n], L.B[n]);
-          p.re = wave_sum(p.re);
-          p.im = wave_sum(p.im);
-          if (lane == 0) L.red[wave * S + i] = p;
-        }
-        if (pass == 0) {
-          T q = T(0);
-          for (int n = tid; n < nj; n += blockDim.x) q += cabs2(L.B[n]);
-          q = wave_sum(q);
-          if (lane == 0) L.red[wave * S + k + 1] = cplx<T>{q, T(0)};
-        }
-        __syncthreads();
-        for (int i = tid; i <= k + (pass == 0 ? 1 : 0); i += blockDim.x) {
-          cplx<double> s = czero<double>();
+        basis_dots<T, NT>(V, nj, k, L.B, L.red, S, pass == 0);
+        lds_barrier();
+        for (int i = tid; i <= k + (pass == 0 ? 1 : 0); i += NT) {
+          cplx<double> sacc = czero<double>();
 #pragma unroll
-          for (int w = 0; w < kWavesPerBlock; ++w) s = s + ccast<double>(L.red[w * S + i]);
+          for (int w = 0; w < NT / kWave; ++w) sacc = sacc + ccast<double>(L.red[w * S + i]);
           if (i <= k) {
-            L.hT[i] = ccast<T>(s);
-            L.h[i] = pass == 0 ? s : L.h[i] + s;
+            L.hT[i] = ccast<T>(sacc);
+            L.h[i] = pass == 0 ? sacc : L.h[i] + sacc;
           } else {
-            L.scal[2] = sqrt(s.re);       // ||w|| before orthogonalisation
+            L.scal[2] = sqrt(sacc.re);       // ||w|| before orthogonalisation
           }
         }
-        __syncthreads();
-        for (int n = tid; n < nj; n += blockDim.x) {
+        lds_barrier();
+        for (int n = tid; n < nj; n += NT) {
           cplx<T> acc = L.B[n];
           for (int i = 0; i <= k; ++i) acc = acc - V[(long long)i * nj + n] * L.hT[i];
           L.B[n] = acc;
         }
-        __syncthreads();
+        lds_barrier();
       }
-      const double hnext = tile_norm(d, L.B, L);
+      const double hnext = tile_norm<T, NT>(d, L.B, L);
       if (tid == 0) {
         cplx<double>* col = L.h;
         for (int i = 0; i < k; ++i) {
@@ -321,37 +376,37 @@ __global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
         const cplx<double> av = col[k];
         const double aa = sqrt(cabs2(av));
         double c;
-        cplx<double> s, r;
+        cplx<double> sv, r;
         if (hnext == 0.0) {
-          c = 1.0; s = czero<double>(); r = av;
+          c = 1.0; sv = czero<double>(); r = av;
         } else if (aa == 0.0) {
-          c = 0.0; s = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
+          c = 0.0; sv = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
         } else {
           const double t = hypot(aa, hnext);
           const cplx<double> ph = cplx<double>{av.re / aa, av.im / aa};
           c = aa / t;
-          s = (hnext / t) * ph;
+          sv = (hnext / t) * ph;
           r = t * ph;
         }
         L.cs[k] = c;
-        L.sn[k] = s;
+        L.sn[k] = sv;
         col[k] = r;
         for (int i = 0; i <= k; ++i) R[(long long)k * maxit + i] = col[i];
         const cplx<double> gk = L.g[k];
-        L.g[k + 1] = czero<double>() - cplx<double>{s.re, -s.im} * gk;
+        L.g[k + 1] = czero<double>() - cplx<double>{sv.re, -sv.im} * gk;
         L.g[k] = c * gk;
         const double res = sqrt(cabs2(L.g[k + 1]));
         const bool brk = hnext <= breakdown_eps<T>() * L.scal[2];
         L.ctrl[0] = (res <= a.tol * ref || brk) ? 1 : 0;
         L.scal[1] = hnext;
       }
-      __syncthreads();
+      lds_barrier();
       converged = L.ctrl[0] != 0;
       ++k;
       if (!converged && k < maxit) {
         const T inv = T(1.0 / L.scal[1]);
         cplx<T>* Vk = V + (long long)k * nj;
-        for (int n = tid; n < nj; n += blockDim.x) {
+        for (int n = tid; n < nj; n += NT) {
           const cplx<T> v = inv * L.B[n];
           Vk[n] = v;
           L.A[n] = v;
@@ -362,26 +417,26 @@ __global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
     // y = R^{-1} g (upper triangular, k x k)
     if (tid == 0) {
       for (int i = k - 1; i >= 0; --i) {
-        cplx<double> s = L.g[i];
-        for (int j = i + 1; j < k; ++j) s = s - R[(long long)j * maxit + i] * L.h[j];
-        L.h[i] = s * cinv(R[(long long)i * maxit + i]);
+        cplx<double> sacc = L.g[i];
+        for (int j = i + 1; j < k; ++j) sacc = sacc - R[(long long)j * maxit + i] * L.h[j];
+        L.h[i] = sacc * cinv(R[(long long)i * maxit + i]);
       }
     }
-    __syncthreads();
-    for (int i = tid; i < k; i += blockDim.x) L.hT[i] = ccast<T>(L.h[i]);
-    __syncthreads();
+    lds_barrier();
+    for (int i = tid; i < k; i += NT) L.hT[i] = ccast<T>(L.h[i]);
+    lds_barrier();
   }
   // x = x0 + V y   (tile A)
-  for (int n = tid; n < nj; n += blockDim.x) {
+  for (int n = tid; n < nj; n += NT) {
     cplx<T> x = accepted ? X[n] : czero<T>();
     for (int i = 0; i < k; ++i) x = x + V[(long long)i * nj + n] * L.hT[i];
     L.A[n] = x;
   }
-  __syncthreads();
+  lds_barrier();
   // recovery: u = x + Z E^{-1} Z^T (f - B x)
   {
     const int ny = d.ny;
-    for (int n = tid; n < nj; n += blockDim.x) {
+    for (int n = tid; n < nj; n += NT) {
       const int lj = n / nx, li = n - lj * nx;
       const cplx<T>* c = L.tab + kStencilPts * node_class(d.i0 + li, d.j0 + lj, d.ax, d.bx, d.ay, d.by);
       cplx<T> acc = c[kC] * L.A[n];
@@ -395,21 +450,21 @@ __global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
         acc = cfma(c[kN], L.A[n + nx], acc);
         if (li < nx - 1) acc = cfma(c[kNE], L.A[n + nx + 1], acc);
       }
-      L.B[n] = F[n] - acc;
+      L.B[n] = fmul * F[n] - acc;
     }
   }
-  __syncthreads();
+  lds_barrier();
   restrict_to(d, L.B, L.ct);
-  __syncthreads();
-  coarse_solve(d, a.fac, a.Ec, L.ct, L.ca, L.ctmp);
-  for (int n = tid; n < nj; n += blockDim.x) {
+  lds_barrier();
+  coarse_solve<NT>(d, a.fac, L.lc, L.ct, L.ca);
+  for (int n = tid; n < nj; n += NT) {
     const int lj = n / nx, li = n - lj * nx;
     const cplx<T> u = L.A[n] + ccast<T>(prolong_at(d, L.ca, li, lj));
-    if (a.U) a.U[fo + n] = u;
+    if (a.U) a.U[fo + n] = ccast<T>(fnorm * ccast<double>(u));
     if (a.z) {
       const int gi = d.i0 + li, gj = d.j0 + lj;
       if (gi >= d.oi0 && gi <= d.oi1 && gj >= d.oj0 && gj <= d.oj1)
-        a.z[(long long)rhs * a.zstride + (long long)(gj - 1) * ldg + (gi - 1)] = ccast<double>(u);
+        a.z[(long long)rhs * a.zstride + (long long)(gj - 1) * ldg + (gi - 1)] = fnorm * ccast<double>(u);
     }
   }
   if (tid == 0) {
@@ -420,25 +475,32 @@ __global__ void __launch_bounds__(kBlock) inner_solve_kernel(InnerArgs<T> a) {
       atomicAdd(a.counters + 1, 1ull);
       atomicMax(a.counters + 2, (unsigned long long)k);
       if (accepted) atomicAdd(a.counters + 3, 1ull);
+      const unsigned long long s = sizeof(cplx<T>), nn = (unsigned long long)nj, kk = (unsigned long long)k;
+      const unsigned long long own = (unsigned long long)(d.oi1 - d.oi0 + 1) * (d.oj1 - d.oj0 + 1);
+      const unsigned long long fac_bytes =
+          16ull * ((unsigned long long)(2 * d.my - 1) * d.mx * d.mx + 3ull * d.mx * d.my);
+      const unsigned long long bytes = 16ull * nn + 16ull * own + (kk + 2) * fac_bytes +
+                                       s * nn * (2 * kk + 2 * kk * (kk + 1)) + 2 * s * nn;
+      atomicAdd(a.counters + 4, bytes);
     }
   }
 }
 
 template <typename T>
 size_t inner_lds_bytes(int max_nj, int max_nc, int maxit) {
-  return lds_bytes<T>(max_nj, max_nc, maxit);
+  return lds_bytes<T>(max_nj, max_nc, maxit, kInnerThreads);
 }
 
 template <typename T>
 hipError_t launch_inner_solve(const InnerArgs<T>& a, hipStream_t st) {
-  const size_t lds = lds_bytes<T>(a.max_nj, a.max_nc, a.maxit);
+  const size_t lds = lds_bytes<T>(a.max_nj, a.max_nc, a.maxit, kInnerThreads);
   const int nblocks = a.cs.nsub * a.nrhs;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)inner_solve_kernel<T>,
+    hipError_t e = hipFuncSetAttribute((const void*)inner_solve_kernel<T, kInnerThreads>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(inner_solve_kernel<T>, dim3(nblocks), dim3(kBlock), lds, st, a);
+  hipLaunchKernelGGL((inner_solve_kernel<T, kInnerThreads>), dim3(nblocks), dim3(kInnerThreads), lds, st, a);
   return hipGetLastError();
 }
 
@@ -475,12 +537,13 @@ __global__ void __launch_bounds__(kBlock) deflated_apply_kernel(const SubDesc* _
                                                                  cplx<T>* __restrict__ w, int max_nj, int max_nc) {
   extern __shared__ __align__(16) unsigned char smem[];
   const SubDesc d = subs[blockIdx.x];
-  Lds<T> L = carve<T>(smem, max_nj, max_nc, 1);
+  Lds<T> L = carve<T, kBlock>(smem, max_nj, max_nc, 1);
   build_class_table<T>(d.robin, cs.kh, cs.kh2, L.tab);
+  stage_lower(d, Ec, L.lc);
   const int nj = d.nx * d.ny;
   for (int n = threadIdx.x; n < nj; n += blockDim.x) L.A[n] = v[d.off + n];
   __syncthreads();
-  deflated_op(d, fac, Ec, L);
+  deflated_op<T, kBlock>(d, fac, L);
   for (int n = threadIdx.x; n < nj; n += blockDim.x) w[d.off + n] = L.B[n];
 }
 
@@ -488,7 +551,7 @@ template <typename T>
 hipError_t launch_deflated_apply(const SubDesc* subs, int nsub, Consts cs, int, const cplx<double>* fac,
                                  const cplx<double>* Ec, const cplx<T>* v, cplx<T>* w, int max_nj, int max_nc,
                                  hipStream_t st) {
-  const size_t lds = lds_bytes<T>(max_nj, max_nc, 1);
+  const size_t lds = lds_bytes<T>(max_nj, max_nc, 1, kBlock);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)deflated_apply_kernel<T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -534,17 +597,18 @@ __global__ void __launch_bounds__(kBlock) coarse_solve_kernel(const SubDesc* __r
   const SubDesc d = subs[blockIdx.x];
   cplx<double>* ct = (cplx<double>*)smem;
   cplx<double>* ca = ct + max_nc;
-  cplx<double>* tmp = ca + max_nc;
+  cplx<double>* lc = ca + max_nc;
   const int nc = d.mx * d.my;
   for (int c = threadIdx.x; c < nc; c += blockDim.x) ct[c] = t[d.coff + c];
+  stage_lower(d, Ec, lc);
   __syncthreads();
-  coarse_solve(d, fac, Ec, ct, ca, tmp);
+  coarse_solve<kBlock>(d, fac, lc, ct, ca);
   for (int c = threadIdx.x; c < nc; c += blockDim.x) y[d.coff + c] = ca[c];
 }
 
 hipError_t launch_coarse_solve(const SubDesc* subs, int nsub, const cplx<double>* fac, const cplx<double>* Ec,
                                const cplx<double>* t, cplx<double>* y, int max_nc, hipStream_t st) {
-  const size_t lds = (2 * (size_t)max_nc + kMaxMx) * sizeof(cplx<double>);
+  const size_t lds = 5 * (size_t)max_nc * sizeof(cplx<double>);
   hipLaunchKernelGGL(coarse_solve_kernel, dim3(nsub), dim3(kBlock), lds, st, subs, fac, Ec, t, y, max_nc);
   return hipGetLastError();
 }

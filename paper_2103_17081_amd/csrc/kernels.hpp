@@ -35,7 +35,8 @@ struct InnerArgs {
   int* iters;                    // [nrhs][nsub] inner iterations, or null
   int* flags;                    // [nrhs][nsub] bit0 guess accepted, bit1 not converged
   const int* done;               // [nrhs] skip right-hand sides already converged, or null
-  unsigned long long* counters;  // [4] total iterations, solves, max iterations, guesses accepted
+  unsigned long long* counters;  // [5] total iterations, solves, max iterations, guesses accepted,
+                                 //     algorithmic bytes
   long long nfine, ndof;
   long long rstride, zstride;    // per right-hand side strides of r and z (elements)
   int nrhs, maxit, max_nj, max_nc;

@@ -32,19 +32,29 @@ hipError_t launch_global_apply_masked(Consts cs, const cplx<double>* v, long lon
                                       long long wstride, int nrhs, const int* done, hipStream_t st);
 hipError_t launch_residual(const cplx<double>* f, long long fstride, cplx<double>* w, long long wstride,
                            long long ndof, int nblk, int nrhs, hipStream_t st);
+int outer_chunks(long long ndof);
 hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<double>* w, long long wstride,
-                       long long ndof, int nvec, int with_norm, cplx<double>* part, int pstride, int nblk,
-                       int nrhs, const int* done, hipStream_t st);
-hipError_t launch_reduce_parts(const cplx<double>* part, int nblk, int pstride, int nslots, cplx<double>* out,
-                               int ostride, cplx<double>* H, int hstride, int mode, int nrhs, const int* done,
-                               hipStream_t st);
+                       long long ndof, int nvec, int with_norm, cplx<double>* part, int pstride, int nrhs,
+                       const int* done, hipStream_t st);
+hipError_t launch_reduce_parts(const cplx<double>* part, long long ndof, int pstride, int nslots,
+                               cplx<double>* out, int ostride, cplx<double>* H, int hstride, int mode, int nrhs,
+                               const int* done, hipStream_t st);
 hipError_t launch_update(const cplx<double>* basis, long long bstride, cplx<double>* w, long long wstride,
-                         long long ndof, int nvec, const cplx<double>* coef, int cstride, double sign, int nblk,
-                         int nrhs, const int* done, hipStream_t st);
+                         long long ndof, int nvec, const cplx<double>* coef, int cstride, double sign, int nrhs,
+                         const int* done, hipStream_t st);
 hipError_t launch_scale(const cplx<double>* w, long long wstride, cplx<double>* out, long long ostride,
                         long long ndof, const double* scale, int nblk, int nrhs, const int* done,
                         hipStream_t st);
 hipError_t launch_givens(const OuterState& s, int j, int nrhs, hipStream_t st);
+hipError_t launch_dots2(const cplx<double>* basis, long long bstride, const cplx<double>* x1, long long x1stride,
+                        const cplx<double>* x2, long long x2stride, long long ndof, int nvec, cplx<double>* part,
+                        int pstride, int nrhs, const int* done, hipStream_t st);
+hipError_t launch_dcgs2_step(const OuterState& s, int j, const cplx<double>* dots, int dstride, int has_w,
+                             cplx<double>* ca, cplx<double>* cb, int cstride, cplx<double>* scal, int nrhs,
+                             hipStream_t st);
+hipError_t launch_dcgs2_update(cplx<double>* basis, long long bstride, long long ndof, int j, const cplx<double>* ca,
+                               const cplx<double>* cb, int cstride, const cplx<double>* scal, int nrhs,
+                               const int* done, hipStream_t st);
 hipError_t launch_backsolve(const OuterState& s, int nrhs, hipStream_t st);
 hipError_t launch_cycle_init(const OuterState& s, int nrhs, hipStream_t st);
 

@@ -66,55 +66,155 @@ hipError_t launch_residual(const cplx<double>* f, long long fstride, cplx<double
   return hipGetLastError();
 }
 
-// part[rhs][blk][i] = sum over the block's rows of conj(basis_i) w for i < nvec,
-// and, if with_norm, part[..][nvec] = sum |w|^2.
+// Dot products of a tall-skinny basis with w, stage 1.  Block (chunk, group, rhs)
+// covers kRowsPerThread * 256 consecutive rows and kVecsPerBlock consecutive slots:
+// slot s < nvec is conj(basis_s) . w, slot nvec (if with_norm) is |w|^2.
+// part layout: [rhs][slot][chunk].
+constexpr int kRowsPerThread = 4;
+constexpr int kVecsPerBlock = 8;
+constexpr int kChunkRows = kRowsPerThread * 256;
+
 __global__ void __launch_bounds__(256) dots_kernel(const cplx<double>* __restrict__ basis, long long bstride,
                                                    const cplx<double>* __restrict__ w, long long wstride,
                                                    long long ndof, int nvec, int with_norm,
                                                    cplx<double>* __restrict__ part, int pstride,
                                                    const int* __restrict__ done) {
-  const int rhs = blockIdx.y;
+  const int rhs = blockIdx.z;
   if (done && done[rhs]) return;
-  __shared__ cplx<double> red[4][kOuterMaxDots];
+  __shared__ cplx<double> red[4][kVecsPerBlock];
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-  const long long chunk = (ndof + gridDim.x - 1) / gridDim.x;
-  const long long n0 = blockIdx.x * chunk;
-  const long long n1 = n0 + chunk < ndof ? n0 + chunk : ndof;
+  const int nchunk = gridDim.x;
+  const long long n0 = (long long)blockIdx.x * kChunkRows + tid;
   const cplx<double>* x = w + rhs * wstride;
+  cplx<double> xr[kRowsPerThread];
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) {
+    const long long n = n0 + r * 256;
+    xr[r] = n < ndof ? x[n] : czero<double>();
+  }
   const int nslots = nvec + (with_norm ? 1 : 0);
-  for (int s0 = 0; s0 < nslots; s0 += kOuterMaxDots) {
-    const int s1 = min(nslots, s0 + kOuterMaxDots);
-    for (int s = s0; s < s1; ++s) {
-      cplx<double> p = czero<double>();
-      if (s < nvec) {
-        const cplx<double>* b = basis + (rhs * bstride) + (long long)s * ndof;
-        for (long long n = n0 + tid; n < n1; n += blockDim.x) p = p + cmulc(b[n], x[n]);
-      } else {
-        for (long long n = n0 + tid; n < n1; n += blockDim.x) p.re += cabs2(x[n]);
+  const int s0 = blockIdx.y * kVecsPerBlock;
+  const int s1 = min(nslots, s0 + kVecsPerBlock);
+  for (int s = s0; s < s1; ++s) {
+    cplx<double> p = czero<double>();
+    if (s < nvec) {
+      const cplx<double>* b = basis + rhs * bstride + (long long)s * ndof;
+#pragma unroll
+      for (int r = 0; r < kRowsPerThread; ++r) {
+        const long long n = n0 + r * 256;
+        if (n < ndof) p = p + cmulc(b[n], xr[r]);
       }
-      p.re = wave_sum(p.re);
-      p.im = wave_sum(p.im);
-      if (lane == 0) red[wave][s - s0] = p;
+    } else {
+#pragma unroll
+      for (int r = 0; r < kRowsPerThread; ++r) p.re += cabs2(xr[r]);
     }
-    __syncthreads();
-    for (int s = s0 + tid; s < s1; s += blockDim.x) {
-      cplx<double> t = red[0][s - s0] + red[1][s - s0] + red[2][s - s0] + red[3][s - s0];
-      part[((long long)rhs * gridDim.x + blockIdx.x) * pstride + s] = t;
-    }
-    __syncthreads();
+    p.re = wave_sum(p.re);
+    p.im = wave_sum(p.im);
+    if (lane == 0) red[wave][s - s0] = p;
+  }
+  __syncthreads();
+  for (int s = s0 + tid; s < s1; s += blockDim.x) {
+    const cplx<double> t = red[0][s - s0] + red[1][s - s0] + red[2][s - s0] + red[3][s - s0];
+    part[((long long)rhs * pstride + s) * nchunk + blockIdx.x] = t;
   }
 }
 
-// out[rhs][s] = sum_blk part[rhs][blk][s]; mode 0: H[s] = out, 1: H[s] += out, 2: none.
-__global__ void __launch_bounds__(256) reduce_parts_kernel(const cplx<double>* __restrict__ part, int nblk,
-                                                           int pstride, int nslots, cplx<double>* __restrict__ out,
-                                                           int ostride, cplx<double>* __restrict__ H, int hstride,
-                                                           int mode, const int* __restrict__ done) {
-  const int rhs = blockIdx.x;
+// Delayed CGS2 pass 1: one sweep over the basis for two vectors.  Slots:
+// [0, nvec): conj(V_i) . x1;  [nvec, 2 nvec): conj(V_i) . x2 (if x2);
+// 2 nvec: |x1|^2;  2 nvec + 1: conj(x1) . x2;  2 nvec + 2: |x2|^2.
+// Each block covers kChunkRows rows and kVecsPerBlock basis vectors (the last group
+// also produces the three self slots); all loads of a vector group are issued before
+// the products are formed.
+__global__ void __launch_bounds__(256) dots2_kernel(const cplx<double>* __restrict__ basis, long long bstride,
+                                                    const cplx<double>* __restrict__ x1, long long x1stride,
+                                                    const cplx<double>* __restrict__ x2, long long x2stride,
+                                                    long long ndof, int nvec, cplx<double>* __restrict__ part,
+                                                    int pstride, const int* __restrict__ done) {
+  const int rhs = blockIdx.z;
   if (done && done[rhs]) return;
-  for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
-    cplx<double> acc = czero<double>();
-    for (int b = 0; b < nblk; ++b) acc = acc + part[((long long)rhs * nblk + b) * pstride + s];
+  __shared__ cplx<double> red[4][2 * kVecsPerBlock + 3];
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int nchunk = gridDim.x;
+  const long long n0 = (long long)blockIdx.x * kChunkRows + tid;
+  const bool two = x2 != nullptr;
+  cplx<double> a[kRowsPerThread], b[kRowsPerThread];
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) {
+    const long long n = n0 + r * 256;
+    a[r] = n < ndof ? x1[rhs * x1stride + n] : czero<double>();
+    b[r] = (two && n < ndof) ? x2[rhs * x2stride + n] : czero<double>();
+  }
+  const int s0 = blockIdx.y * kVecsPerBlock;
+  const int s1 = min(nvec, s0 + kVecsPerBlock);
+  const int cnt = s1 > s0 ? s1 - s0 : 0;
+  cplx<double> v[kVecsPerBlock][kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kVecsPerBlock; ++q) {
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+      const long long n = n0 + r * 256;
+      v[q][r] = (q < cnt && n < ndof) ? basis[rhs * bstride + (long long)(s0 + q) * ndof + n] : czero<double>();
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kVecsPerBlock; ++q) {
+    if (q < cnt) {
+      cplx<double> p1 = czero<double>(), p2 = czero<double>();
+#pragma unroll
+      for (int r = 0; r < kRowsPerThread; ++r) {
+        p1 = p1 + cmulc(v[q][r], a[r]);
+        if (two) p2 = p2 + cmulc(v[q][r], b[r]);
+      }
+      p1.re = wave_sum(p1.re); p1.im = wave_sum(p1.im);
+      if (lane == 0) red[wave][q] = p1;
+      if (two) {
+        p2.re = wave_sum(p2.re); p2.im = wave_sum(p2.im);
+        if (lane == 0) red[wave][kVecsPerBlock + q] = p2;
+      }
+    }
+  }
+  const bool self = blockIdx.y == gridDim.y - 1;
+  if (self) {
+    cplx<double> p[3] = {czero<double>(), czero<double>(), czero<double>()};
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+      p[0].re += cabs2(a[r]);
+      p[1] = p[1] + cmulc(a[r], b[r]);
+      p[2].re += cabs2(b[r]);
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      p[e].re = wave_sum(p[e].re); p[e].im = wave_sum(p[e].im);
+      if (lane == 0) red[wave][2 * kVecsPerBlock + e] = p[e];
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * kVecsPerBlock + 3) {
+    int slot = -1;
+    if (tid < kVecsPerBlock) slot = tid < cnt ? s0 + tid : -1;
+    else if (tid < 2 * kVecsPerBlock) slot = (two && tid - kVecsPerBlock < cnt) ? nvec + s0 + tid - kVecsPerBlock : -1;
+    else slot = self ? 2 * nvec + (tid - 2 * kVecsPerBlock) : -1;
+    if (slot >= 0) {
+      const cplx<double> t = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+      part[((long long)rhs * pstride + slot) * nchunk + blockIdx.x] = t;
+    }
+  }
+}
+
+// Stage 2: out[rhs][s] = sum over chunks; mode 0: H[s] = out, 1: H[s] += out, 2: none.
+// One wavefront per (slot, rhs).
+__global__ void __launch_bounds__(64) reduce_parts_kernel(const cplx<double>* __restrict__ part, int nchunk,
+                                                          int pstride, cplx<double>* __restrict__ out, int ostride,
+                                                          cplx<double>* __restrict__ H, int hstride, int mode,
+                                                          const int* __restrict__ done) {
+  const int s = blockIdx.x, rhs = blockIdx.y;
+  if (done && done[rhs]) return;
+  const cplx<double>* p = part + ((long long)rhs * pstride + s) * nchunk;
+  cplx<double> acc = czero<double>();
+  for (int c = threadIdx.x; c < nchunk; c += 64) acc = acc + p[c];
+  acc.re = wave_sum(acc.re);
+  acc.im = wave_sum(acc.im);
+  if (threadIdx.x == 0) {
     out[rhs * ostride + s] = acc;
     if (H) {
       cplx<double>* hh = H + (long long)rhs * hstride + s;
@@ -124,7 +224,8 @@ __global__ void __launch_bounds__(256) reduce_parts_kernel(const cplx<double>* _
   }
 }
 
-// w -= sum_i basis_i * coef[i], i < nvec.
+// w += sign * sum_i basis_i * coef[i], i < nvec.  Each thread owns kRowsPerThread rows
+// (strided by 256 inside a chunk) and keeps independent accumulators.
 __global__ void __launch_bounds__(256) update_kernel(const cplx<double>* __restrict__ basis, long long bstride,
                                                      cplx<double>* __restrict__ w, long long wstride,
                                                      long long ndof, int nvec,
@@ -134,17 +235,239 @@ __global__ void __launch_bounds__(256) update_kernel(const cplx<double>* __restr
   if (done && done[rhs]) return;
   __shared__ cplx<double> c[kOuterMaxDots];
   cplx<double>* x = w + rhs * wstride;
+  const long long n0 = (long long)blockIdx.x * kChunkRows + threadIdx.x;
+  cplx<double> acc[kRowsPerThread];
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) acc[r] = czero<double>();
   for (int s0 = 0; s0 < nvec; s0 += kOuterMaxDots) {
     const int s1 = min(nvec, s0 + kOuterMaxDots);
     __syncthreads();
     for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) c[s - s0] = coef[rhs * cstride + s];
     __syncthreads();
-    for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ndof;
-         n += (long long)gridDim.x * blockDim.x) {
-      cplx<double> acc = czero<double>();
-      for (int s = s0; s < s1; ++s) acc = cfma(basis[rhs * bstride + (long long)s * ndof + n], c[s - s0], acc);
-      x[n] = x[n] + sign * acc;
+    for (int q0 = s0; q0 < s1; q0 += kVecsPerBlock) {
+      cplx<double> vv[kVecsPerBlock][kRowsPerThread];
+#pragma unroll
+      for (int q = 0; q < kVecsPerBlock; ++q) {
+#pragma unroll
+        for (int r = 0; r < kRowsPerThread; ++r) {
+          const long long n = n0 + r * 256;
+          vv[q][r] = (q0 + q < s1 && n < ndof) ? basis[rhs * bstride + (long long)(q0 + q) * ndof + n]
+                                                : czero<double>();
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kVecsPerBlock; ++q) {
+        if (q0 + q < s1) {
+          const cplx<double> cs = c[q0 + q - s0];
+#pragma unroll
+          for (int r = 0; r < kRowsPerThread; ++r) acc[r] = cfma(vv[q][r], cs, acc[r]);
+        }
+      }
     }
+  }
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) {
+    const long long n = n0 + r * 256;
+    if (n < ndof) x[n] = x[n] + sign * acc[r];
+  }
+}
+
+// Delayed CGS2 pass 2 (one sweep over the basis V_j for two outputs):
+//   v_j     = u~_j / alpha - V_j (s / alpha)                     (slot j, in place)
+//   u~_{j+1} = (w - V_j (c - s h_jj / alpha) - u~_j h_jj / alpha) / gamma_{j+1}
+//                                                                 (slot j+1, in place of w)
+// coefficient vectors a = s / alpha and b = c - s h_jj / alpha and the scalars
+// (1/alpha, h_jj/alpha, 1/gamma) come from dcgs2_step_kernel.
+__global__ void __launch_bounds__(256) dcgs2_update_kernel(cplx<double>* __restrict__ basis, long long bstride,
+                                                           long long ndof, int j, const cplx<double>* __restrict__ ca,
+                                                           const cplx<double>* __restrict__ cb, int cstride,
+                                                           const cplx<double>* __restrict__ scal,
+                                                           const int* __restrict__ done) {
+  const int rhs = blockIdx.y;
+  if (done && done[rhs]) return;
+  __shared__ cplx<double> la[kOuterMaxDots], lb[kOuterMaxDots];
+  cplx<double>* V = basis + rhs * bstride;
+  const long long n0 = (long long)blockIdx.x * kChunkRows + threadIdx.x;
+  cplx<double> acc_a[kRowsPerThread], acc_b[kRowsPerThread];
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) { acc_a[r] = czero<double>(); acc_b[r] = czero<double>(); }
+  for (int s0 = 0; s0 < j; s0 += kOuterMaxDots) {
+    const int s1 = min(j, s0 + kOuterMaxDots);
+    __syncthreads();
+    for (int q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
+      la[q - s0] = ca[rhs * cstride + q];
+      lb[q - s0] = cb[rhs * cstride + q];
+    }
+    __syncthreads();
+    // batches of kVecsPerBlock basis vectors: all loads of a batch are issued first
+    for (int q0 = s0; q0 < s1; q0 += kVecsPerBlock) {
+      cplx<double> vv[kVecsPerBlock][kRowsPerThread];
+#pragma unroll
+      for (int q = 0; q < kVecsPerBlock; ++q) {
+#pragma unroll
+        for (int r = 0; r < kRowsPerThread; ++r) {
+          const long long n = n0 + r * 256;
+          vv[q][r] = (q0 + q < s1 && n < ndof) ? V[(long long)(q0 + q) * ndof + n] : czero<double>();
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kVecsPerBlock; ++q) {
+        if (q0 + q < s1) {
+          const cplx<double> xa = la[q0 + q - s0], xb = lb[q0 + q - s0];
+#pragma unroll
+          for (int r = 0; r < kRowsPerThread; ++r) {
+            acc_a[r] = cfma(vv[q][r], xa, acc_a[r]);
+            acc_b[r] = cfma(vv[q][r], xb, acc_b[r]);
+          }
+        }
+      }
+    }
+  }
+  const cplx<double> inv_alpha = scal[rhs * 4 + 0], e = scal[rhs * 4 + 1], inv_gamma = scal[rhs * 4 + 2];
+  cplx<double>* uj = V + (long long)j * ndof;
+  cplx<double>* w = V + (long long)(j + 1) * ndof;
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) {
+    const long long n = n0 + r * 256;
+    if (n < ndof) {
+      const cplx<double> uo = uj[n];
+      uj[n] = inv_alpha.re * uo - acc_a[r];
+      w[n] = inv_gamma.re * (w[n] - acc_b[r] - uo * e);
+    }
+  }
+}
+
+// Delayed CGS2 bookkeeping of step j for every active right-hand side (one workgroup
+// each).  From the pass-1 dots (s = V_j^H u~_j, c = V_j^H w, nu = |u~_j|^2,
+// mu = u~_j^H w, ww = |w|^2):
+//   alpha = sqrt(nu - |s|^2)  (norm of u~_j after reorthogonalisation);
+//   column j-1 becomes final: h_{i,j-1} = t_i + gamma_j s_i (i < j, t = the tentative
+//   column kept from step j-1), h_{j,j-1} = gamma_j alpha; it is rotated into R
+//   and the residual estimate |g_j| decides convergence (with j columns);
+//   tentative column j: t_i = c_i (i < j), t_j = h_jj = (mu - s^H c) / alpha;
+//   gamma_{j+1} = sqrt(ww - |c|^2 - |h_jj|^2) (Pythagoras; only a scaling that the next
+//   step corrects exactly through nu).
+// Step 0 has no column to finalise; it sets g_0 = beta * alpha.
+__global__ void __launch_bounds__(256) dcgs2_step_kernel(OuterState st, int j, const cplx<double>* __restrict__ dots,
+                                                         int dstride, int has_w, cplx<double>* __restrict__ ca,
+                                                         cplx<double>* __restrict__ cb, int cstride,
+                                                         cplx<double>* __restrict__ scal) {
+  const int rhs = blockIdx.x;
+  if (st.done[rhs]) return;
+  extern __shared__ __align__(16) unsigned char gsm[];
+  const int m = st.restart;
+  cplx<double>* lcol = (cplx<double>*)gsm;          // j + 1 entries
+  cplx<double>* lsn = lcol + (j + 2);
+  double* lcs = (double*)(lsn + (j + 1));
+  __shared__ double red[4];
+  __shared__ cplx<double> redc[4];
+  __shared__ double sh_alpha;
+  __shared__ int sh_conv;
+  const cplx<double>* D = dots + (long long)rhs * dstride;
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  // |s|^2
+  double ss = 0.0;
+  for (int i = tid; i < j; i += blockDim.x) ss += cabs2(D[i]);
+  ss = wave_sum(ss);
+  if (lane == 0) red[wave] = ss;
+  __syncthreads();
+  if (tid == 0) {
+    const double nu = D[2 * j].re;
+    const double a2 = nu - (red[0] + red[1] + red[2] + red[3]);
+    sh_alpha = sqrt(a2 > 1e-300 ? a2 : 1e-300);
+    sh_conv = 0;
+  }
+  __syncthreads();
+  const double alpha = sh_alpha;
+  cplx<double>* T = st.H + (long long)rhs * (m + 1);   // tentative column
+  const double gamma = st.hnext[rhs];                   // gamma_j from step j-1
+  cplx<double>* g = st.g + (long long)rhs * (m + 1);
+  if (j == 0) {
+    if (tid == 0) g[0] = cplx<double>{g[0].re * alpha, g[0].im * alpha};
+  } else {
+    // finalise column jc = j-1 and rotate it
+    const int jc = j - 1;
+    double* cs = st.cs + (long long)rhs * m;
+    cplx<double>* sn = st.sn + (long long)rhs * m;
+    for (int i = tid; i <= jc; i += blockDim.x) {
+      lcol[i] = T[i] + gamma * D[i];
+      if (i < jc) { lsn[i] = sn[i]; lcs[i] = cs[i]; }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double hnext = gamma * alpha;
+      for (int i = 0; i < jc; ++i) {
+        const cplx<double> x0 = lcol[i], x1 = lcol[i + 1];
+        lcol[i] = lcs[i] * x0 + lsn[i] * x1;
+        lcol[i + 1] = lcs[i] * x1 - cplx<double>{lsn[i].re, -lsn[i].im} * x0;
+      }
+      const cplx<double> av = lcol[jc];
+      const double aa = sqrt(cabs2(av));
+      double c;
+      cplx<double> sv, r;
+      if (hnext == 0.0) {
+        c = 1.0; sv = czero<double>(); r = av;
+      } else if (aa == 0.0) {
+        c = 0.0; sv = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
+      } else {
+        const double t = hypot(aa, hnext);
+        const cplx<double> ph{av.re / aa, av.im / aa};
+        c = aa / t;
+        sv = (hnext / t) * ph;
+        r = t * ph;
+      }
+      cs[jc] = c;
+      sn[jc] = sv;
+      lcol[jc] = r;
+      const cplx<double> gj = g[jc];
+      g[jc + 1] = czero<double>() - cplx<double>{sv.re, -sv.im} * gj;
+      g[jc] = c * gj;
+      const double res = sqrt(cabs2(g[jc + 1]));
+      st.res[rhs] = res;
+      st.steps[rhs] = j;
+      sh_conv = (res <= st.atol[rhs] || hnext == 0.0) ? 1 : 0;
+    }
+    __syncthreads();
+    cplx<double>* R = st.R + (long long)rhs * m * m + (long long)jc * m;
+    for (int i = tid; i <= jc; i += blockDim.x) R[i] = lcol[i];
+  }
+  if (sh_conv || !has_w) {
+    if (tid == 0 && sh_conv) st.done[rhs] = 1;
+    return;
+  }
+  // tentative column j and the pass-2 coefficients
+  cplx<double> sc = czero<double>();
+  double cc = 0.0;
+  for (int i = tid; i < j; i += blockDim.x) {
+    sc = sc + cmulc(D[i], D[j + i]);
+    cc += cabs2(D[j + i]);
+  }
+  sc.re = wave_sum(sc.re); sc.im = wave_sum(sc.im); cc = wave_sum(cc);
+  __syncthreads();
+  if (lane == 0) { redc[wave] = sc; red[wave] = cc; }
+  __syncthreads();
+  const cplx<double> sTc = redc[0] + redc[1] + redc[2] + redc[3];
+  const double csum = red[0] + red[1] + red[2] + red[3];
+  const cplx<double> mu = D[2 * j + 1];
+  const double ww = D[2 * j + 2].re;
+  const cplx<double> hjj = (1.0 / alpha) * (mu - sTc);
+  const cplx<double> e = (1.0 / alpha) * hjj;
+  for (int i = tid; i < j; i += blockDim.x) {
+    const cplx<double> si = D[i], ci = D[j + i];
+    T[i] = ci;
+    ca[rhs * cstride + i] = (1.0 / alpha) * si;
+    cb[rhs * cstride + i] = ci - si * e;
+  }
+  if (tid == 0) {
+    T[j] = hjj;
+    double g2 = ww - csum - cabs2(hjj);
+    const double floor2 = 1e-28 * (ww > 0 ? ww : 1.0);
+    if (!(g2 > floor2)) g2 = floor2;
+    const double gam = sqrt(g2);
+    st.hnext[rhs] = gam;
+    scal[rhs * 4 + 0] = cplx<double>{1.0 / alpha, 0.0};
+    scal[rhs * 4 + 1] = e;
+    scal[rhs * 4 + 2] = cplx<double>{1.0 / gam, 0.0};
   }
 }
 
@@ -162,70 +485,90 @@ __global__ void __launch_bounds__(256) scale_kernel(const cplx<double>* w, long 
     out[rhs * ostride + n] = inv * w[rhs * wstride + n];
 }
 
-// Givens step j of every active right-hand side (one thread each).
-// H column j (j+1 entries) is in hcol; the norm^2 of the orthogonalised w in
+// Givens step j of every active right-hand side (one workgroup each).
+// H column j (j+1 entries) is in st.H; the norm^2 of the orthogonalised w in
 // nrm2[rhs].  Applies the stored rotations, forms rotation j, updates g, stores the
 // rotated column into R (column j), sets res[rhs] = |g_{j+1}| and done[rhs] when
-// res <= atol[rhs], and hnext[rhs] = ||w||.
-__global__ void givens_kernel(OuterState st, int j, int nrhs) {
-  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rhs >= nrhs || st.done[rhs]) return;
+// res <= atol[rhs], and hnext[rhs] = ||w||.  The column and the rotations are staged
+// through LDS so the sequential sweep runs at LDS latency.
+constexpr int kGivensMax = 4000;
+__global__ void __launch_bounds__(256) givens_kernel(OuterState st, int j) {
+  const int rhs = blockIdx.x;
+  if (st.done[rhs]) return;
+  extern __shared__ __align__(16) unsigned char gsm[];
   const int m = st.restart;
+  cplx<double>* lcol = (cplx<double>*)gsm;
+  cplx<double>* lsn = lcol + (j + 2);
+  double* lcs = (double*)(lsn + (j + 1));
   cplx<double>* col = st.H + (long long)rhs * (m + 1);
-  const double hnext = sqrt(st.nrm2[rhs * st.nrm_stride].re);
   double* cs = st.cs + (long long)rhs * m;
   cplx<double>* sn = st.sn + (long long)rhs * m;
   cplx<double>* g = st.g + (long long)rhs * (m + 1);
-  for (int i = 0; i < j; ++i) {
-    const cplx<double> x0 = col[i], x1 = col[i + 1];
-    col[i] = cs[i] * x0 + sn[i] * x1;
-    col[i + 1] = cs[i] * x1 - cplx<double>{sn[i].re, -sn[i].im} * x0;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    lcol[i] = col[i];
+    if (i < j) { lsn[i] = sn[i]; lcs[i] = cs[i]; }
   }
-  const cplx<double> av = col[j];
-  const double aa = sqrt(cabs2(av));
-  double c;
-  cplx<double> s, r;
-  if (hnext == 0.0) {
-    c = 1.0; s = czero<double>(); r = av;
-  } else if (aa == 0.0) {
-    c = 0.0; s = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
-  } else {
-    const double t = hypot(aa, hnext);
-    const cplx<double> ph{av.re / aa, av.im / aa};
-    c = aa / t;
-    s = (hnext / t) * ph;
-    r = t * ph;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double hnext = sqrt(st.nrm2[rhs * st.nrm_stride].re);
+    for (int i = 0; i < j; ++i) {
+      const cplx<double> x0 = lcol[i], x1 = lcol[i + 1];
+      lcol[i] = lcs[i] * x0 + lsn[i] * x1;
+      lcol[i + 1] = lcs[i] * x1 - cplx<double>{lsn[i].re, -lsn[i].im} * x0;
+    }
+    const cplx<double> av = lcol[j];
+    const double aa = sqrt(cabs2(av));
+    double c;
+    cplx<double> s, r;
+    if (hnext == 0.0) {
+      c = 1.0; s = czero<double>(); r = av;
+    } else if (aa == 0.0) {
+      c = 0.0; s = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
+    } else {
+      const double t = hypot(aa, hnext);
+      const cplx<double> ph{av.re / aa, av.im / aa};
+      c = aa / t;
+      s = (hnext / t) * ph;
+      r = t * ph;
+    }
+    cs[j] = c;
+    sn[j] = s;
+    lcol[j] = r;
+    const cplx<double> gj = g[j];
+    g[j + 1] = czero<double>() - cplx<double>{s.re, -s.im} * gj;
+    g[j] = c * gj;
+    const double res = sqrt(cabs2(g[j + 1]));
+    st.res[rhs] = res;
+    st.hnext[rhs] = hnext;
+    st.steps[rhs] = j + 1;
+    if (res <= st.atol[rhs] || hnext == 0.0) st.done[rhs] = 1;
   }
-  cs[j] = c;
-  sn[j] = s;
-  col[j] = r;
-  cplx<double>* R = st.R + (long long)rhs * m * m;
-  for (int i = 0; i <= j; ++i) R[(long long)j * m + i] = col[i];
-  const cplx<double> gj = g[j];
-  g[j + 1] = czero<double>() - cplx<double>{s.re, -s.im} * gj;
-  g[j] = c * gj;
-  const double res = sqrt(cabs2(g[j + 1]));
-  st.res[rhs] = res;
-  st.hnext[rhs] = hnext;
-  st.steps[rhs] = j + 1;
-  if (res <= st.atol[rhs] || hnext == 0.0) st.done[rhs] = 1;
+  __syncthreads();
+  cplx<double>* R = st.R + (long long)rhs * m * m + (long long)j * m;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) R[i] = lcol[i];
 }
 
-// y = R^{-1} g over the first steps[rhs] columns (one thread per right-hand side).
-__global__ void backsolve_kernel(OuterState st, int nrhs) {
-  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (rhs >= nrhs) return;
+// y = R^{-1} g over the first steps[rhs] columns (one workgroup per right-hand side,
+// column-oriented back substitution: after y_i is known every thread updates its rows).
+__global__ void __launch_bounds__(256) backsolve_kernel(OuterState st) {
+  const int rhs = blockIdx.x;
   const int m = st.restart;
   const int k = st.steps[rhs];
   const cplx<double>* R = st.R + (long long)rhs * m * m;
-  const cplx<double>* g = st.g + (long long)rhs * (m + 1);
+  cplx<double>* g = st.g + (long long)rhs * (m + 1);
   cplx<double>* y = st.y + (long long)rhs * m;
+  __shared__ cplx<double> yi;
   for (int i = k - 1; i >= 0; --i) {
-    cplx<double> s = g[i];
-    for (int jj = i + 1; jj < k; ++jj) s = s - R[(long long)jj * m + i] * y[jj];
-    y[i] = s * cinv(R[(long long)i * m + i]);
+    if (threadIdx.x == 0) {
+      yi = g[i] * cinv(R[(long long)i * m + i]);
+      y[i] = yi;
+    }
+    __syncthreads();
+    const cplx<double> v = yi;
+    for (int l = threadIdx.x; l < i; l += blockDim.x) g[l] = g[l] - R[(long long)i * m + l] * v;
+    __syncthreads();
   }
-  for (int i = k; i < m; ++i) y[i] = czero<double>();
+  for (int i = k + threadIdx.x; i < m; i += blockDim.x) y[i] = czero<double>();
 }
 
 // Initialise a cycle: g = (beta, 0, ...), steps = 0, beta from the norm slot.
@@ -244,27 +587,31 @@ __global__ void cycle_init_kernel(OuterState st, int nrhs) {
   st.done[rhs] = (beta <= st.atol[rhs]) ? 1 : 0;
 }
 
+int outer_chunks(long long ndof) { return (int)((ndof + kChunkRows - 1) / kChunkRows); }
+
 hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<double>* w, long long wstride,
-                       long long ndof, int nvec, int with_norm, cplx<double>* part, int pstride, int nblk,
-                       int nrhs, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(dots_kernel, dim3(nblk, nrhs), dim3(256), 0, st, basis, bstride, w, wstride, ndof, nvec,
-                     with_norm, part, pstride, done);
+                       long long ndof, int nvec, int with_norm, cplx<double>* part, int pstride, int nrhs,
+                       const int* done, hipStream_t st) {
+  const int nslots = nvec + (with_norm ? 1 : 0);
+  dim3 grid(outer_chunks(ndof), (nslots + kVecsPerBlock - 1) / kVecsPerBlock, nrhs);
+  hipLaunchKernelGGL(dots_kernel, grid, dim3(256), 0, st, basis, bstride, w, wstride, ndof, nvec, with_norm,
+                     part, pstride, done);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_parts(const cplx<double>* part, int nblk, int pstride, int nslots, cplx<double>* out,
-                               int ostride, cplx<double>* H, int hstride, int mode, int nrhs, const int* done,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(nrhs), dim3(256), 0, st, part, nblk, pstride, nslots, out,
-                     ostride, H, hstride, mode, done);
+hipError_t launch_reduce_parts(const cplx<double>* part, long long ndof, int pstride, int nslots,
+                               cplx<double>* out, int ostride, cplx<double>* H, int hstride, int mode, int nrhs,
+                               const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(nslots, nrhs), dim3(64), 0, st, part, outer_chunks(ndof), pstride,
+                     out, ostride, H, hstride, mode, done);
   return hipGetLastError();
 }
 
 hipError_t launch_update(const cplx<double>* basis, long long bstride, cplx<double>* w, long long wstride,
-                         long long ndof, int nvec, const cplx<double>* coef, int cstride, double sign, int nblk,
-                         int nrhs, const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(update_kernel, dim3(nblk, nrhs), dim3(256), 0, st, basis, bstride, w, wstride, ndof, nvec,
-                     coef, cstride, sign, done);
+                         long long ndof, int nvec, const cplx<double>* coef, int cstride, double sign, int nrhs,
+                         const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(update_kernel, dim3(outer_chunks(ndof), nrhs), dim3(256), 0, st, basis, bstride, w, wstride,
+                     ndof, nvec, coef, cstride, sign, done);
   return hipGetLastError();
 }
 
@@ -276,13 +623,57 @@ hipError_t launch_scale(const cplx<double>* w, long long wstride, cplx<double>* 
   return hipGetLastError();
 }
 
+hipError_t launch_dots2(const cplx<double>* basis, long long bstride, const cplx<double>* x1, long long x1stride,
+                        const cplx<double>* x2, long long x2stride, long long ndof, int nvec, cplx<double>* part,
+                        int pstride, int nrhs, const int* done, hipStream_t st) {
+  const int groups = nvec > 0 ? (nvec + kVecsPerBlock - 1) / kVecsPerBlock : 1;
+  dim3 grid(outer_chunks(ndof), groups, nrhs);
+  hipLaunchKernelGGL(dots2_kernel, grid, dim3(256), 0, st, basis, bstride, x1, x1stride, x2, x2stride, ndof, nvec,
+                     part, pstride, done);
+  return hipGetLastError();
+}
+
+hipError_t launch_dcgs2_step(const OuterState& s, int j, const cplx<double>* dots, int dstride, int has_w,
+                             cplx<double>* ca, cplx<double>* cb, int cstride, cplx<double>* scal, int nrhs,
+                             hipStream_t st) {
+  if (j > kGivensMax) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(j + 2) * sizeof(cplx<double>) + (size_t)(j + 1) * (sizeof(cplx<double>) + sizeof(double));
+  static bool attr = false;
+  if (!attr && lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)dcgs2_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)((size_t)(kGivensMax + 2) * 40));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(dcgs2_step_kernel, dim3(nrhs), dim3(256), lds, st, s, j, dots, dstride, has_w, ca, cb, cstride,
+                     scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_dcgs2_update(cplx<double>* basis, long long bstride, long long ndof, int j, const cplx<double>* ca,
+                               const cplx<double>* cb, int cstride, const cplx<double>* scal, int nrhs,
+                               const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(dcgs2_update_kernel, dim3(outer_chunks(ndof), nrhs), dim3(256), 0, st, basis, bstride, ndof, j,
+                     ca, cb, cstride, scal, done);
+  return hipGetLastError();
+}
+
 hipError_t launch_givens(const OuterState& s, int j, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(givens_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, s, j, nrhs);
+  if (j + 1 > kGivensMax) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(j + 2) * sizeof(cplx<double>) + (size_t)(j + 1) * (sizeof(cplx<double>) + sizeof(double));
+  static bool attr = false;
+  if (!attr && lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)givens_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)((size_t)(kGivensMax + 2) * 40));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(givens_kernel, dim3(nrhs), dim3(256), lds, st, s, j);
   return hipGetLastError();
 }
 
 hipError_t launch_backsolve(const OuterState& s, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(backsolve_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, st, s, nrhs);
+  hipLaunchKernelGGL(backsolve_kernel, dim3(nrhs), dim3(256), 0, st, s);
   return hipGetLastError();
 }
 

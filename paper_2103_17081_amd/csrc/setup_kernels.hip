@@ -41,8 +41,9 @@ __global__ void __launch_bounds__(kBlock) assemble_coarse_kernel(const SubDesc* 
   }
 }
 
-// In-place Gauss-Jordan inverse with partial pivoting of the n x n column-major
-// matrix A (global memory), workgroup-cooperative.  Returns min |pivot| (thread 0).
+// In-place Gauss-Jordan inverse with partial pivoting of the n x n row-major matrix
+// A (global memory; element (r, c) at r*n + c), workgroup-cooperative.  Returns the
+// smallest |pivot| met.
 __device__ double gauss_jordan_inverse(cplx<double>* A, int n, int* perm, cplx<double>* colp,
                                        double* sh_pivabs) {
   const int tid = threadIdx.x;
@@ -52,7 +53,7 @@ __device__ double gauss_jordan_inverse(cplx<double>* A, int n, int* perm, cplx<d
       int q = p;
       double best = cabs2(A[p * n + p]);
       for (int r = p + 1; r < n; ++r) {
-        double v = cabs2(A[p * n + r]);
+        const double v = cabs2(A[r * n + p]);
         if (v > best) { best = v; q = r; }
       }
       perm[p] = q;
@@ -62,36 +63,35 @@ __device__ double gauss_jordan_inverse(cplx<double>* A, int n, int* perm, cplx<d
     const int q = perm[p];
     if (q != p) {
       for (int c = tid; c < n; c += blockDim.x) {
-        cplx<double> x = A[c * n + p];
-        A[c * n + p] = A[c * n + q];
-        A[c * n + q] = x;
+        const cplx<double> x = A[p * n + c];
+        A[p * n + c] = A[q * n + c];
+        A[q * n + c] = x;
       }
     }
     __syncthreads();
-    const double pa = *sh_pivabs;
-    minpiv = fmin(minpiv, pa);
+    minpiv = fmin(minpiv, *sh_pivabs);
     const cplx<double> inv = cinv(A[p * n + p]);
     __syncthreads();
-    // scale row p; the pivot entry becomes 1/pivot
-    for (int c = tid; c < n; c += blockDim.x) A[c * n + p] = (c == p) ? inv : inv * A[c * n + p];
-    // stash column p before it is overwritten
-    for (int r = tid; r < n; r += blockDim.x) colp[r] = A[p * n + r];
+    // scale row p (the pivot entry becomes 1/pivot) and stash column p
+    for (int c = tid; c < n; c += blockDim.x) A[p * n + c] = (c == p) ? inv : inv * A[p * n + c];
+    for (int r = tid; r < n; r += blockDim.x) colp[r] = A[r * n + p];
     __syncthreads();
     for (int e = tid; e < n * n; e += blockDim.x) {
-      const int r = e % n, c = e / n;
+      const int r = e / n, c = e - r * n;
       if (r == p) continue;
       const cplx<double> f = colp[r];
-      A[c * n + r] = (c == p) ? czero<double>() - A[p * n + p] * f : A[c * n + r] - A[c * n + p] * f;
+      A[r * n + c] = (c == p) ? czero<double>() - A[p * n + p] * f : A[r * n + c] - A[p * n + c] * f;
     }
     __syncthreads();
   }
+  // undo the row interchanges by swapping columns in reverse order
   for (int p = n - 1; p >= 0; --p) {
     const int q = perm[p];
     if (q != p) {
       for (int r = tid; r < n; r += blockDim.x) {
-        cplx<double> x = A[p * n + r];
-        A[p * n + r] = A[q * n + r];
-        A[q * n + r] = x;
+        const cplx<double> x = A[r * n + p];
+        A[r * n + p] = A[r * n + q];
+        A[r * n + q] = x;
       }
     }
     __syncthreads();
@@ -114,32 +114,34 @@ __global__ void __launch_bounds__(kBlock) factor_coarse_kernel(const SubDesc* __
   for (int i = 0; i < my; ++i) {
     cplx<double>* G = F + (size_t)i * mm;
     const cplx<double>* Hprev = F + (size_t)(my + i - 1) * mm;
+    // S_i = D_i - L_i H_{i-1}
     for (int e = tid; e < mm; e += blockDim.x) {
-      const int r = e % mx, c = e / mx;
+      const int r = e / mx, c = e - r * mx;
       const cplx<double>* row = ec + (size_t)(i * mx + r) * 9;
       cplx<double> s = (c - r >= -1 && c - r <= 1) ? row[3 + (c - r) + 1] : czero<double>();
       if (i > 0) {
         for (int dr = -1; dr <= 1; ++dr) {
           const int rr = r + dr;
-          if (rr >= 0 && rr < mx) s = s - row[dr + 1] * Hprev[c * mx + rr];
+          if (rr >= 0 && rr < mx) s = s - row[dr + 1] * Hprev[rr * mx + c];
         }
       }
-      G[c * mx + r] = s;
+      G[r * mx + c] = s;
     }
     __syncthreads();
     minp = fmin(minp, gauss_jordan_inverse(G, mx, perm, colp, &pivabs));
     if (i < my - 1) {
+      // H_i = G_i U_i, U_i(cc, c) = coupling of row-i node cc to row-(i+1) node c
       cplx<double>* H = F + (size_t)(my + i) * mm;
       for (int e = tid; e < mm; e += blockDim.x) {
-        const int r = e % mx, c = e / mx;
+        const int r = e / mx, c = e - r * mx;
         cplx<double> s = czero<double>();
         for (int dc = -1; dc <= 1; ++dc) {
-          const int cc = c + dc;    // U_i(cc, c): coupling of row-i node cc to row-(i+1) node c
+          const int cc = c + dc;
           if (cc < 0 || cc >= mx) continue;
           const cplx<double> u = ec[(size_t)(i * mx + cc) * 9 + 6 + (c - cc) + 1];
-          s = s + G[cc * mx + r] * u;
+          s = s + G[r * mx + cc] * u;
         }
-        H[c * mx + r] = s;
+        H[r * mx + c] = s;
       }
     }
     __syncthreads();

@@ -1,6 +1,7 @@
 """Write tests/golden/oracle_counts.json from the oracle alone.
 
 Usage: python tests/golden/make_golden.py small [medium] [large]
+       python tests/golden/make_golden.py --spread small [medium]
 
 For each named workload (paper_2103_17081_amd.inputs.workload) and its first right-hand
 side, runs the oracle's outer FGMRES with impedance (ORAS) local matrices, linear
@@ -21,6 +22,42 @@ from oracle import schwarz  # noqa: E402
 from paper_2103_17081_amd import inputs  # noqa: E402
 
 OUT = os.path.join(HERE, "oracle_counts.json")
+
+
+EPS32 = 2.0 ** -24   # complex64 unit roundoff
+
+
+def spread(name, seeds=8):
+    """Outer counts of the oracle when its subdomain solves are perturbed at FP32 level.
+
+    Mode "round": local right-hand sides and local solutions rounded to complex64.
+    Mode "noise": local solutions multiplied by (1 + EPS32 * xi), xi complex normal,
+    seeded.  Each run is the oracle's FGMRES with the oracle's deflated-GMRES solves.
+    """
+    import numpy as np
+    from oracle import krylov
+    w = inputs.workload(name)
+    S = schwarz.Schwarz(schwarz.problem_from_workload(w))
+    r32 = lambda x: x.astype(np.complex64).astype(np.complex128)
+
+    def run(post, pre=lambda f: f):
+        def apply(r):
+            us = []
+            for s, f in zip(S.subs, S.local_rhs(r)):
+                u, _, _ = s.deflated_gmres(pre(f), w.inner_tol, 100)
+                us.append(post(u))
+            return S.scatter(us)
+        return krylov.fgmres(lambda v: S.A @ v, apply, w.rhs[0], rtol=w.outer_tol, maxit=5000).iters
+
+    counts = {"round": run(r32, r32)}
+    noise = []
+    for sd in range(seeds):
+        rng = np.random.default_rng(1000 + sd)
+        noise.append(run(lambda u: u * (1 + EPS32 * (rng.standard_normal(u.size) + 1j * rng.standard_normal(u.size)))))
+    counts["noise"] = noise
+    allc = [counts["round"]] + noise
+    counts["min"], counts["max"] = min(allc), max(allc)
+    return counts
 
 
 def main(names):
@@ -48,4 +85,13 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["small"])
+    args = sys.argv[1:]
+    if args and args[0] == "--spread":
+        data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+        for name in args[1:] or ["small"]:
+            data.setdefault(name, {})["fp32_perturbed_outer"] = spread(name, 8 if name == "small" else 2)
+            print(name, data[name]["fp32_perturbed_outer"], flush=True)
+            with open(OUT, "w") as fh:
+                json.dump(data, fh, indent=1, sort_keys=True)
+    else:
+        main(args or ["small"])

@@ -7,9 +7,12 @@
   one), and the recovered local solutions agree to 1e-8 where the counts match;
 * the preconditioner z = M^{-1} r agrees with the oracle's to 1e-8 (FP64 inner);
 * end to end: true relative residual <= 1e-6 and outer counts within +-1 of the
-  oracle for the FP64 inner solver; for the FP32 inner solver the residual bound is
-  the same and the outer-count difference is reported (bounded loosely, since the
-  inexact inner iterates differ at the 1e-7 level and FGMRES amplifies that);
+  oracle for the FP64 inner solver.  For the FP32 inner solver the residual bound is
+  the same; its outer count must lie within the spread the FP64 oracle itself shows
+  when its subdomain solves are perturbed at FP32 rounding level (rounded to
+  complex64, or multiplied by 1 + 2^-24 xi), widened by 2.  The loose inner tolerance
+  makes the subdomain GMRES stopping decisions, and hence the outer count, sensitive
+  to perturbations of that size (tests/golden/make_golden.py --spread);
 * at the full large size, sampled subdomains of one preconditioner application are
   recomputed by the oracle from the same input.
 """
@@ -132,7 +135,10 @@ def test_solve_fp32_inner(torch, name):
         print(name, "fp32", st, "true relres", rel, "outer diff vs fp64 oracle", diff, flush=True)
         assert st["status"] == "DD_OK"
         assert rel <= 1e-6
-        assert abs(diff) <= max(2, 0.05 * gold["outer_iters"])
+        sp = gold.get("fp32_perturbed_outer")
+        lo = min(sp["min"], gold["outer_iters"]) - 2 if sp else gold["outer_iters"] - 2
+        hi = max(sp["max"], gold["outer_iters"]) + 2 if sp else gold["outer_iters"] + 2
+        assert lo <= st["outer_iters"] <= hi, (lo, hi)
 
 
 @pytest.mark.parametrize("prec", [64, 32])
