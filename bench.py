@@ -32,6 +32,25 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "DD-FGMRES time-to-solution (rel res 1e-6) & subdomain solves/s, chosen vs plain"
 
 
+def recorded_traffic():
+    """Calibrated HBM bytes per dispatch from the committed counter summary, if the kernel
+    sources are unchanged since the counters were taken (else {})."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "large_solve_hbm_traffic.md")
+    if not os.path.exists(path):
+        return {}
+    text = open(path).read()
+    if "```json" not in text:
+        return {}
+    block = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2103_17081_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        h.update(open(p, "rb").read())
+    return block["traffic_bytes_per_dispatch"] if h.hexdigest() == block["csrc_sha256"] else {}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +131,7 @@ def main():
     relres = true_relres(torch, chosen, f, u)
     solves = sum(s["subdomain_solves"] for s in stats)
     launches = sum(s["inner_launches"] for s in stats)
+    traffic = recorded_traffic() if args.workload == "large" else {}
     kernels = []
     for name, ms_key, b_key in (("inner_solve_kernel<float, 512>", "ms_inner", "inner_bytes"),
                                 ("dots2_kernel", "ms_dots", "dots_bytes"),
@@ -120,7 +140,7 @@ def main():
         by = sum(s[b_key] for s in stats)
         ach = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         kernels.append({"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": ach / HBM_PEAK_GBS, "traffic": None, "launches": launches,
+                        "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get(name), "launches": launches,
                         "total_ms": ms, "avg_launch_ms": ms / max(launches, 1),
                         "bytes_per_launch": by / max(launches, 1)})
     dom = max(kernels, key=lambda k: k["total_ms"])
