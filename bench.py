@@ -8,12 +8,14 @@ k = 200, 20 points per wavelength (N = 637, 404,496 unknowns), 16 x 16 subdomain
 with widths perturbed by +-25%, three seeded Gaussian sources, inner tolerance 1e-2.
 
 `value` is whole-job throughput in subdomain solves per second of the chosen form
-(complex64 subdomain Krylov work, FP64 coarse solves and outer FGMRES);
-`ms_per_step` is its time to solution.  The all-FP64 ("plain") form is timed beside
+(complex64 subdomain Krylov work, FP64 coarse solves and outer FGMRES, outer steps
+replayed from a captured hipGraph); `ms_per_step` is its time to solution.  The all-FP64 ("plain") form is timed beside
 it.  `kernels` gives, for the batched subdomain-solve kernel and the two basis sweeps
 of the outer delayed-CGS2 Arnoldi, algorithmic bytes (counted per launch by the
-library) over durations from HIP events recorded on the library's stream; `roofline`
-is the one with the largest total time.  The CPU baseline is the oracle timed on a
+library) over durations from HIP events recorded on the library's stream around each
+kernel, in one more solve of the same handle and inputs with the steps launched one
+by one right after the timed solves (HIP cannot time events inside graph replays);
+`roofline` is the one with the largest total time.  The CPU baseline is the oracle timed on a
 bounded sample of the same workload (its first outer iterations).
 """
 
@@ -126,18 +128,27 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     chosen = make_solver(w, 32)
+    tune_report = chosen.autotune(None)      # launch configuration measured on this problem (set-up)
     t, u, stats = timed_solves(torch, chosen, f, args.steps, args.warmup)
     last = stats[-1]
     relres = true_relres(torch, chosen, f, u)
     solves = sum(s["subdomain_solves"] for s in stats)
-    launches = sum(s["inner_launches"] for s in stats)
+    # Per-kernel durations: the same handle and inputs, outer steps launched one by one
+    # with HIP events around every kernel (events cannot be timed inside graph replays).
+    chosen.set_graph(False)
+    torch.cuda.synchronize()
+    _, inst = chosen.solve(f)
+    torch.cuda.synchronize()
+    chosen.set_graph(True)
+    stats_k = [inst]
+    launches = inst["precond_applies"]
     traffic = recorded_traffic() if args.workload == "large" else {}
     kernels = []
     for name, ms_key, b_key in (("inner_solve_kernel<float, 512>", "ms_inner", "inner_bytes"),
                                 ("dots2_kernel", "ms_dots", "dots_bytes"),
                                 ("dcgs2_update_kernel", "ms_update", "update_bytes")):
-        ms = sum(s[ms_key] for s in stats)
-        by = sum(s[b_key] for s in stats)
+        ms = sum(s[ms_key] for s in stats_k)
+        by = sum(s[b_key] for s in stats_k)
         ach = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         kernels.append({"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get(name), "launches": launches,
@@ -165,21 +176,25 @@ def main():
                    "precond_applies": last["precond_applies"],
                    "avg_inner_iters": last["inner_iters_total"] / max(last["subdomain_solves"], 1),
                    "true_relres": relres, "status": last["status"],
-                   "ms_phase": {"inner": last["ms_inner"], "spmv": last["ms_spmv"],
-                                "orth": last["ms_orth"], "dots": last["ms_dots"], "update": last["ms_update"]}},
+                   "graph_replays": last["graph_replays"], "ms_outer_steps": last["ms_steps"],
+                   "autotune": tune_report.split("\n")[0],
+                   "ms_phase_instrumented_solve": {"inner": inst["ms_inner"], "spmv": inst["ms_spmv"],
+                                                   "orth": inst["ms_orth"], "dots": inst["ms_dots"],
+                                                   "bookkeeping": inst["ms_other"], "update": inst["ms_update"],
+                                                   "all_steps": inst["ms_steps"]}},
         "roofline": dom,
         "kernels": kernels,
     }
     chosen.close()
     if not args.no_plain:
         plain = make_solver(w, 64)
-        tp, up, sp = timed_solves(torch, plain, f, 1, 0)
+        plain.autotune(None)
+        tp, up, sp = timed_solves(torch, plain, f, 1, 1)
         out["plain"] = {"time_to_solution_s": tp, "outer_iters": sp[-1]["outer_iters"],
                         "subdomain_solves_per_s": sp[-1]["subdomain_solves"] / tp,
                         "avg_inner_iters": sp[-1]["inner_iters_total"] / max(sp[-1]["subdomain_solves"], 1),
                         "true_relres": true_relres(torch, plain, f, up), "status": sp[-1]["status"],
-                        "ms_phase": {"inner": sp[-1]["ms_inner"], "spmv": sp[-1]["ms_spmv"],
-                                     "orth": sp[-1]["ms_orth"], "other": sp[-1]["ms_other"]}}
+                        "graph_replays": sp[-1]["graph_replays"]}
         out["chosen_speedup_vs_plain"] = tp / (t / args.steps)
         plain.close()
     if not args.no_cpu:

@@ -71,6 +71,8 @@ typedef struct {
   int outer_maxit;     /* total FGMRES iterations */
   int outer_restart;   /* FGMRES restart length; <= 0 means outer_maxit (no restart) */
   int nrhs;            /* independent right-hand sides solved together */
+  int use_graph;       /* 1: outer steps replayed from a captured hipGraph (default), 0: launched one by one */
+  int graph_steps;     /* outer steps per graph replay; convergence is read back once per replay */
 } dd_params;
 
 typedef struct {
@@ -89,9 +91,10 @@ typedef struct {
      (milliseconds, summed over the solve), and launch counts. */
   double ms_inner;             /* batched subdomain-solve kernel (preconditioner) */
   double ms_spmv;              /* global stencil A z_j */
-  double ms_orth;              /* Gram-Schmidt dot products, updates, norms */
-  double ms_other;             /* Givens, scaling, final combination */
-  int inner_launches;
+  double ms_orth;              /* outer delayed CGS2: dot sweep + bookkeeping + update sweep */
+  double ms_other;             /* of which the bookkeeping (reductions, Givens rotations) */
+  int inner_launches;          /* outer steps enqueued (including no-op steps after convergence
+                                  inside a graph replay) */
   /* Algorithmic bytes of the subdomain-solve kernel summed over its launches: per solve,
      gather 16 n_j + scatter 16 owned_j + (k_j + 2) coarse-factor reads of
      16 ((2 my - 1) mx^2 + 3 mx my) bytes + Krylov traffic s n_j (2 k_j + 2 k_j (k_j + 1))
@@ -104,11 +107,16 @@ typedef struct {
      16 nd (j + 4) bytes (nd unknowns, complex128). */
   double ms_dots, ms_update;
   double dots_bytes, update_bytes;
+  int graph_replays;           /* graph launches (0 when use_graph is off) */
+  int timed_steps;             /* outer steps launched one by one; the per-phase times above cover
+                                  only these (events cannot be timed inside graph replays) */
+  double ms_steps;             /* all outer steps, from events around each replay or batch */
 } dd_stats;
 
 /* Fill *p with the defaults: k = 20, ppwl = 10, 2 x 2 uniform subdomains, overlap 1,
    impedance local matrices, linear deflation, FP64 inner, inner_tol 1e-2,
-   inner_maxit 100, outer_tol 1e-6, outer_maxit 3000, no restart, nrhs 1. */
+   inner_maxit 100, outer_tol 1e-6, outer_maxit 3000, no restart, nrhs 1, graph replay of
+   8 outer steps. */
 void dd_default_params(dd_params* p);
 
 /* Build the mesh, the partition, every E_j = Z_j^T B_j Z_j (Sec. 2, eq. 4) and its
@@ -128,6 +136,17 @@ dd_status dd_apply_preconditioner(dd_handle* h, const void* r, void* z, void* st
 dd_status dd_solve(dd_handle* h, const void* f, void* u, void* stream, dd_stats* stats);
 
 dd_status dd_destroy(dd_handle* h);
+/* Switch graph replay of the outer steps on or off for later dd_solve calls (the
+   per-phase event timings of dd_stats are only available with it off). */
+dd_status dd_set_graph(dd_handle* h, int use_graph);
+/* Autotuner: time candidate launch configurations on this handle's problem with HIP events
+   and keep the fastest: threads per subdomain-solve workgroup (256 or 512), launch order
+   (largest tile first or natural) and the workgroup count of the outer dot sweep.  With
+   cache_path (may be NULL) a line "<signature> | <choice>" is looked up first (signature:
+   GPU architecture, grid, partition hash, overlap, local condition, precision, inner_maxit,
+   nrhs, restart) and appended after measuring.  Uses the handle's workspaces: do not call
+   it while a solve is in flight.  report (may be NULL) receives a text summary. */
+dd_status dd_autotune(dd_handle* h, const char* cache_path, void* stream, char* report, int report_len);
 const char* dd_last_error(void);
 
 int64_t dd_num_dofs(const dd_handle* h);

@@ -45,6 +45,8 @@ class Params(ctypes.Structure):
         ("outer_maxit", ctypes.c_int),
         ("outer_restart", ctypes.c_int),
         ("nrhs", ctypes.c_int),
+        ("use_graph", ctypes.c_int),
+        ("graph_steps", ctypes.c_int),
     ]
 
 
@@ -68,6 +70,9 @@ class Stats(ctypes.Structure):
         ("ms_update", ctypes.c_double),
         ("dots_bytes", ctypes.c_double),
         ("update_bytes", ctypes.c_double),
+        ("graph_replays", ctypes.c_int),
+        ("timed_steps", ctypes.c_int),
+        ("ms_steps", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -88,6 +93,8 @@ _SIGS = {
     "dd_apply_preconditioner": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "dd_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(Stats)]),
     "dd_destroy": (ctypes.c_int, [_VP]),
+    "dd_set_graph": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "dd_autotune": (ctypes.c_int, [_VP, ctypes.c_char_p, _VP, ctypes.c_char_p, ctypes.c_int]),
     "dd_last_error": (ctypes.c_char_p, []),
     "dd_num_dofs": (ctypes.c_int64, [_VP]),
     "dd_num_subdomains": (ctypes.c_int, [_VP]),
@@ -168,7 +175,7 @@ class Solver:
                  cuts_x=None, cuts_y=None, overlap: int = 1, local_bc: str = "impedance",
                  deflation: str = "linear", inner_precision: int = 64, inner_tol: float = 1e-2,
                  inner_maxit: int = 100, outer_tol: float = 1e-6, outer_maxit: int = 3000,
-                 outer_restart: int = 0, nrhs: int = 1):
+                 outer_restart: int = 0, nrhs: int = 1, use_graph: bool = True, graph_steps: int = 8):
         p = default_params()
         p.k, p.ppwl, p.n_intervals = k, ppwl, n_intervals
         p.px, p.py = px, py
@@ -188,6 +195,8 @@ class Solver:
         p.inner_tol, p.inner_maxit = inner_tol, inner_maxit
         p.outer_tol, p.outer_maxit, p.outer_restart = outer_tol, outer_maxit, outer_restart
         p.nrhs = nrhs
+        p.use_graph = 1 if use_graph else 0
+        p.graph_steps = graph_steps
         self.params = p
         self._h = ctypes.c_void_p()
         torch = _torch()
@@ -239,6 +248,15 @@ class Solver:
         _check(lib().dd_coarse_matrix(self._h, j, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       ctypes.byref(piv)), "dd_coarse_matrix")
         return out.view(np.complex128).reshape(mx * my, 9), piv.value
+
+    def autotune(self, cache_path=None) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        path = cache_path.encode() if cache_path else None
+        _check(lib().dd_autotune(self._h, path, _stream(self.torch), buf, len(buf)), "dd_autotune")
+        return buf.value.decode()
+
+    def set_graph(self, on: bool):
+        _check(lib().dd_set_graph(self._h, 1 if on else 0), "dd_set_graph")
 
     # -- the three calls of the method --
     def apply_preconditioner(self, r, z=None):

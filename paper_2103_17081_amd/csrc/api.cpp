@@ -43,6 +43,8 @@ dd_status fail(dd_status s, const std::string& msg) {
 
 constexpr int kOuterBlocks = 1024;   // workgroups of the grid-stride outer kernels
 constexpr int kMaxRestart = 4000;    // Givens kernel stages a restart cycle in LDS
+constexpr int kMaxGraphSteps = 64;   // outer steps per captured graph
+constexpr int kEvPerStep = 6;        // phase events recorded per outer step
 
 }  // namespace
 
@@ -86,6 +88,15 @@ struct dd_handle {
   double* res_h = nullptr;      // pinned
   hipEvent_t ev[8] = {};        // phase timers of dd_solve
   bool ev_ok = false;
+  int* jdev = nullptr;          // device-side outer step index
+  // launch configuration (dd_autotune)
+  int inner_nt = ddh::kInnerThreads;
+  bool lpt = true;              // subdomain solves launched largest tile first
+  int dots_blocks = 0;          // grid of the outer dot sweep (0 = default)
+  std::vector<hipEvent_t> sev;  // per-step phase events, kEvPerStep per step slot
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   std::vector<void*> allocs;
 
   template <typename T>
@@ -102,6 +113,14 @@ struct dd_handle {
     if (ev_ok)
       for (int e = 0; e < 8; ++e) (void)hipEventDestroy(ev[e]);
     ev_ok = false;
+    for (hipEvent_t e : sev) (void)hipEventDestroy(e);
+    sev.clear();
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    graph_exec = nullptr;
+    graph = nullptr;
+    cap_stream = nullptr;
     if (done_h) (void)hipHostFree(done_h);
     if (res_h) (void)hipHostFree(res_h);
     done_h = nullptr;
@@ -128,6 +147,8 @@ void dd_default_params(dd_params* p) {
   p->outer_maxit = 3000;   /* also the restart length unless outer_restart > 0 */
   p->outer_restart = 0;
   p->nrhs = 1;
+  p->use_graph = 1;
+  p->graph_steps = 8;
 }
 
 const char* dd_last_error(void) { return g_last_error.c_str(); }
@@ -156,6 +177,8 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   if (!(p->outer_tol > 0.0 && p->outer_tol < 1.0)) return fail(DD_EINVAL, "outer_tol must be in (0, 1)");
   if (p->outer_maxit < 1) return fail(DD_EINVAL, "outer_maxit must be >= 1");
   if (p->nrhs < 1 || p->nrhs > 64) return fail(DD_EINVAL, "nrhs must be in [1, 64]");
+  if (p->use_graph && (p->graph_steps < 1 || p->graph_steps > kMaxGraphSteps))
+    return fail(DD_EINVAL, "graph_steps must be in [1, 64]");
   auto cuts = [&](const int* c, int parts, std::vector<int>& out) -> dd_status {
     out.resize(parts + 1);
     for (int q = 0; q <= parts; ++q) out[q] = c ? c[q] : (int)(((long long)q * n) / parts);
@@ -275,19 +298,24 @@ ddh::InnerArgs<T> inner_args(dd_handle* h) {
   a.max_nj = h->max_nj;
   a.max_nc = h->max_nc;
   a.tol = h->p.inner_tol;
+  a.nt = h->inner_nt;
+  a.order = h->lpt ? h->order : nullptr;
   return a;
 }
 
 // Preconditioner apply: z = M^{-1} r over all right-hand sides (those with done set are skipped).
 dd_status run_apply(dd_handle* h, const cplx<double>* r, long long rstride, cplx<double>* z, long long zstride,
-                    const int* done, hipStream_t st) {
+                    const int* done, hipStream_t st, const int* jdev = nullptr, long long rslot = 0,
+                    long long zslot = 0) {
   if (h->prec == 32) {
     auto a = inner_args<float>(h);
     a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot;
     DD_HIP(ddh::launch_inner_solve<float>(a, st));
   } else {
     auto a = inner_args<double>(h);
     a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot;
     DD_HIP(ddh::launch_inner_solve<double>(a, st));
   }
   return DD_OK;
@@ -367,6 +395,15 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     DD_TRY(h->alloc(&o.atol, h->nrhs));
     DD_TRY(h->alloc(&o.steps, h->nrhs));
     DD_TRY(h->alloc(&o.done, h->nrhs));
+    DD_TRY(h->alloc(&o.applies, h->nrhs));
+    DD_TRY(h->alloc(&o.sweep_bytes, 2));
+    DD_TRY(h->alloc(&h->jdev, 1));
+    const int slots = std::max(1, h->p.graph_steps);
+    h->sev.resize((size_t)slots * kEvPerStep);
+    for (auto& e : h->sev) DD_HIP(hipEventCreate(&e));
+    if (h->prec == 32) DD_HIP(ddh::configure_inner<float>(h->max_nj, h->max_nc, h->maxit));
+    else DD_HIP(ddh::configure_inner<double>(h->max_nj, h->max_nc, h->maxit));
+    DD_HIP(ddh::configure_outer());
     o.nrm2 = h->coef;
     o.nrm_stride = h->pstride;
     o.rtol = h->p.outer_tol;
@@ -389,6 +426,14 @@ dd_status dd_destroy(dd_handle* h) {
   if (!h) return DD_OK;
   h->release();
   delete h;
+  return DD_OK;
+}
+
+dd_status dd_set_graph(dd_handle* h, int use_graph) {
+  DD_TRY(check_handle(h));
+  if (use_graph && (h->p.graph_steps < 1 || h->p.graph_steps > kMaxGraphSteps))
+    return fail(DD_EINVAL, "graph_steps must be in [1, 64]");
+  h->p.use_graph = use_graph ? 1 : 0;
   return DD_OK;
 }
 
@@ -426,6 +471,58 @@ dd_status dd_apply_preconditioner(dd_handle* h, const void* r, void* z, void* st
   return run_apply(h, (const cplx<double>*)r, h->ndof, (cplx<double>*)z, h->ndof, nullptr, (hipStream_t)stream);
 }
 
+// One outer FGMRES step j (j read from h->jdev by every kernel): z_j = M^{-1} v~_j,
+// w = A z_j, delayed-CGS2 dot sweep + bookkeeping + update sweep, j += 1.  Right-hand
+// sides whose done flag is set skip all of it.  `slot` selects the phase events.
+static dd_status enqueue_outer_step(dd_handle* h, int slot, hipStream_t st, bool timed) {
+  const int m = h->restart, nr = h->nrhs;
+  const long long nd = h->ndof;
+  const long long vstr = (long long)(m + 1) * nd, zstr = (long long)m * nd;
+  ddh::OuterState& o = h->os;
+  const ddh::StepRef sr = ddh::device_step(h->jdev);
+  hipEvent_t* ev = h->sev.data() + (size_t)slot * kEvPerStep;
+  auto mark = [&](int e) -> dd_status {
+    if (timed) DD_HIP(hipEventRecord(ev[e], st));
+    return DD_OK;
+  };
+  DD_TRY(mark(0));
+  DD_TRY(run_apply(h, h->Vo, vstr, h->Zo, zstr, o.done, st, h->jdev, nd, nd));
+  DD_TRY(mark(1));
+  DD_HIP(ddh::launch_global_apply_masked(h->cs, h->Zo, zstr, h->Vo + nd, vstr, nr, o.done, st, sr, nd, nd));
+  DD_TRY(mark(2));
+  DD_HIP(ddh::launch_dots2(h->Vo, vstr, nullptr, 0, nullptr, 0, nd, sr, 1, m, h->part, h->pstride, nr, o.done, st,
+                           h->dots_blocks));
+  DD_TRY(mark(3));
+  DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, sr, 2, 3, m, h->coef, h->pstride, nullptr, 0, 2, nr,
+                                  o.done, st));
+  DD_HIP(ddh::launch_dcgs2_step(o, sr, m, nd, h->coef, h->pstride, 1, h->ca, h->cb, m, h->scal, nr, st));
+  DD_TRY(mark(4));
+  DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, sr, h->ca, h->cb, m, h->scal, nr, o.done, st));
+  DD_TRY(mark(5));
+  DD_HIP(ddh::launch_advance_step(h->jdev, st));
+  return DD_OK;
+}
+
+// Capture graph_steps consecutive outer steps once per handle (on a private stream:
+// the caller's stream may be the legacy default stream, which cannot be captured).
+static dd_status ensure_graph(dd_handle* h) {
+  if (h->graph_exec) return DD_OK;
+  if (!h->cap_stream) DD_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  DD_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  dd_status s = DD_OK;
+  for (int q = 0; q < h->p.graph_steps && s == DD_OK; ++q) s = enqueue_outer_step(h, q, h->cap_stream, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (s != DD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(DD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  h->graph = g;
+  DD_HIP(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+  return DD_OK;
+}
+
 dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stats* stats) {
   DD_TRY(check_handle(h));
   if (!fv || !uv || fv == uv) return fail(DD_EINVAL, "f and u must be distinct non-null device pointers");
@@ -436,13 +533,17 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
   const long long nd = h->ndof;
   const long long vstr = (long long)(m + 1) * nd, zstr = (long long)m * nd;
   ddh::OuterState& o = h->os;
+  const int S = h->p.use_graph ? h->p.graph_steps : 1;
+  if (h->p.use_graph) DD_TRY(ensure_graph(h));
   DD_HIP(hipMemsetAsync(h->counters, 0, 5 * sizeof(unsigned long long), st));
+  DD_HIP(hipMemsetAsync(o.applies, 0, nr * sizeof(int), st));
+  DD_HIP(hipMemsetAsync(o.sweep_bytes, 0, 2 * sizeof(unsigned long long), st));
   DD_HIP(hipMemsetAsync(u, 0, (size_t)nr * nd * sizeof(cplx<double>), st));
-  double ms[4] = {0, 0, 0, 0};
-  double ms_dots = 0, ms_upd = 0, b_dots = 0, b_upd = 0;
-  int launches = 0;
+  double ms[5] = {0, 0, 0, 0, 0};   // inner, global stencil, dot sweep, bookkeeping, update sweep
+  double ms_steps = 0.0;            // all outer steps (graph replays and eager steps)
+  int launches = 0, replays = 0, timed_steps = 0;
   float el = 0.f;
-  int applies = 0, columns = 0;
+  int steps_run = 0, columns = 0;
   bool all_done = false;
   std::vector<int> steps_h(nr);
   o.first_cycle = 1;
@@ -457,60 +558,54 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
     return DD_OK;
   };
   while (true) {
-    // beta = ||r||, g = (beta, 0, ..), v~_0 = r / beta
+    // beta = ||r||, g = (beta, 0, ..), v~_0 = r / beta, j = 0
     DD_HIP(ddh::launch_dots(h->Vo, vstr, h->Vo, vstr, nd, 0, 1, h->part, h->pstride, nr, nullptr, st));
-    DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, 1, h->coef, h->pstride, nullptr, 0, 2, nr, nullptr, st));
+    DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, ddh::host_step(0), 0, 1, 0, h->coef, h->pstride,
+                                    nullptr, 0, 2, nr, nullptr, st));
     DD_HIP(ddh::launch_cycle_init(o, nr, st));
     DD_HIP(ddh::launch_scale(h->Vo, vstr, h->Vo, vstr, nd, o.hnext, kOuterBlocks, nr, o.done, st));
+    DD_HIP(hipMemsetAsync(h->jdev, 0, sizeof(int), st));
     o.first_cycle = 0;
     DD_TRY(sync_done());
     if (all_done) break;
     int j = 0;
-    for (; j < m && applies < h->p.outer_maxit; ++j) {
-      cplx<double>* vj = h->Vo + (long long)j * nd;
-      cplx<double>* zj = h->Zo + (long long)j * nd;
-      cplx<double>* w = h->Vo + (long long)(j + 1) * nd;
-      int act = 0;          // right-hand sides active in this step
-      for (int q = 0; q < nr; ++q) act += h->done_h[q] ? 0 : 1;
-      // z_j = M^{-1} v~_j (flexible: stored), w = A z_j
+    while (j < m && steps_run < h->p.outer_maxit) {
+      const int batch = std::min(S, std::min(m - j, h->p.outer_maxit - steps_run));
+      const bool replay = h->p.use_graph && batch == S;
       DD_HIP(hipEventRecord(h->ev[0], st));
-      DD_TRY(run_apply(h, vj, vstr, zj, zstr, o.done, st));
-      DD_HIP(hipEventRecord(h->ev[1], st));
-      DD_HIP(ddh::launch_global_apply_masked(h->cs, zj, zstr, w, vstr, nr, o.done, st));
-      DD_HIP(hipEventRecord(h->ev[2], st));
-      // delayed CGS2: one dot sweep, bookkeeping (finalises column j-1), one update sweep
-      DD_HIP(ddh::launch_dots2(h->Vo, vstr, vj, vstr, w, vstr, nd, j, h->part, h->pstride, nr, o.done, st));
-      DD_HIP(hipEventRecord(h->ev[5], st));
-      DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, 2 * j + 3, h->coef, h->pstride, nullptr, 0, 2, nr,
-                                      o.done, st));
-      DD_HIP(ddh::launch_dcgs2_step(o, j, h->coef, h->pstride, 1, h->ca, h->cb, m, h->scal, nr, st));
-      DD_HIP(hipEventRecord(h->ev[6], st));
-      DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, j, h->ca, h->cb, m, h->scal, nr, o.done, st));
-      DD_HIP(hipEventRecord(h->ev[7], st));
-      DD_HIP(hipEventRecord(h->ev[3], st));
-      DD_HIP(hipEventRecord(h->ev[4], st));
-      ++applies;
-      ++launches;
-      DD_TRY(sync_done());
-      for (int e = 0; e < 4; ++e) {
-        DD_HIP(hipEventElapsedTime(&el, h->ev[e], h->ev[e + 1]));
-        ms[e] += el;
+      if (replay) {
+        DD_HIP(hipGraphLaunch(h->graph_exec, st));
+        ++replays;
+      } else {
+        for (int q = 0; q < batch; ++q) DD_TRY(enqueue_outer_step(h, q, st, true));
       }
-      DD_HIP(hipEventElapsedTime(&el, h->ev[2], h->ev[5]));
-      ms_dots += el;
-      DD_HIP(hipEventElapsedTime(&el, h->ev[6], h->ev[7]));
-      ms_upd += el;
-      b_dots += 16.0 * nd * (j + 2) * act;
-      b_upd += 16.0 * nd * (j + 4) * act;
+      DD_HIP(hipEventRecord(h->ev[1], st));
+      j += batch;
+      steps_run += batch;
+      launches += batch;
+      DD_TRY(sync_done());
+      DD_HIP(hipEventElapsedTime(&el, h->ev[0], h->ev[1]));
+      ms_steps += el;
+      if (!replay) {
+        timed_steps += batch;
+        for (int q = 0; q < batch; ++q) {
+          hipEvent_t* ev = h->sev.data() + (size_t)q * kEvPerStep;
+          for (int e = 0; e < 5; ++e) {
+            DD_HIP(hipEventElapsedTime(&el, ev[e], ev[e + 1]));
+            ms[e] += el;
+          }
+        }
+      }
       if (all_done) break;
     }
     if (!all_done && j == m) {
       // end of a cycle: finalise column m-1 from v~_m alone
-      DD_HIP(ddh::launch_dots2(h->Vo, vstr, h->Vo + (long long)m * nd, vstr, nullptr, 0, nd, m, h->part, h->pstride,
-                               nr, o.done, st));
-      DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, 2 * m + 3, h->coef, h->pstride, nullptr, 0, 2, nr,
-                                      o.done, st));
-      DD_HIP(ddh::launch_dcgs2_step(o, m, h->coef, h->pstride, 0, h->ca, h->cb, m, h->scal, nr, st));
+      DD_HIP(ddh::launch_dots2(h->Vo, vstr, h->Vo + (long long)m * nd, vstr, nullptr, 0, nd, ddh::host_step(m), 0, m,
+                               h->part, h->pstride, nr, o.done, st, h->dots_blocks));
+      DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, ddh::host_step(m), 2, 3, m, h->coef, h->pstride,
+                                      nullptr, 0, 2, nr, o.done, st));
+      DD_HIP(ddh::launch_dcgs2_step(o, ddh::host_step(m), m, nd, h->coef, h->pstride, 0, h->ca, h->cb, m, h->scal,
+                                    nr, st));
       DD_TRY(sync_done());
     }
     // u += Z y over the columns each right-hand side finalised in this cycle
@@ -520,20 +615,23 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
     const int kmax = *std::max_element(steps_h.begin(), steps_h.end());
     columns += kmax;
     DD_HIP(ddh::launch_update(h->Zo, zstr, u, nd, nd, kmax, o.y, m, 1.0, nr, nullptr, st));
-    if (all_done || applies >= h->p.outer_maxit) break;
+    if (all_done || steps_run >= h->p.outer_maxit) break;
     // restart: r = f - A u
     DD_HIP(ddh::launch_global_apply_masked(h->cs, u, nd, h->Vo, vstr, nr, nullptr, st));
     DD_HIP(ddh::launch_residual(f, nd, h->Vo, vstr, nd, kOuterBlocks, nr, st));
   }
   if (stats) {
-    unsigned long long c[5];
+    unsigned long long c[5], sb[2];
+    std::vector<int> app(nr);
     DD_HIP(hipMemcpyAsync(c, h->counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipMemcpyAsync(sb, o.sweep_bytes, sizeof(sb), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipMemcpyAsync(app.data(), o.applies, nr * sizeof(int), hipMemcpyDeviceToHost, st));
     DD_HIP(hipMemcpyAsync(h->res_h, o.res, nr * sizeof(double), hipMemcpyDeviceToHost, st));
     std::vector<double> at(nr);
     DD_HIP(hipMemcpyAsync(at.data(), o.atol, nr * sizeof(double), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
     stats->outer_iters = columns;
-    stats->precond_applies = applies;
+    stats->precond_applies = *std::max_element(app.begin(), app.end());
     stats->converged = all_done ? 1 : 0;
     stats->inner_iters_total = (long long)c[0];
     stats->subdomain_solves = (long long)c[1];
@@ -542,13 +640,16 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
     stats->inner_bytes = (double)c[4];
     stats->ms_inner = ms[0];
     stats->ms_spmv = ms[1];
-    stats->ms_orth = ms[2];
+    stats->ms_orth = ms[2] + ms[3] + ms[4];
     stats->ms_other = ms[3];
+    stats->ms_dots = ms[2];
+    stats->ms_update = ms[4];
+    stats->dots_bytes = (double)sb[0];
+    stats->update_bytes = (double)sb[1];
     stats->inner_launches = launches;
-    stats->ms_dots = ms_dots;
-    stats->ms_update = ms_upd;
-    stats->dots_bytes = b_dots;
-    stats->update_bytes = b_upd;
+    stats->graph_replays = replays;
+    stats->timed_steps = timed_steps;
+    stats->ms_steps = ms_steps;
     double worst = 0.0;
     for (int q = 0; q < nr; ++q) {
       const double rel = at[q] > 0 ? h->res_h[q] / (at[q] / h->p.outer_tol) : 0.0;
@@ -557,6 +658,141 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
     stats->final_res_estimate = worst;
   }
   return all_done ? DD_OK : fail(DD_ENOTCONV, "outer FGMRES reached outer_maxit");
+}
+
+// ---- autotuner ---------------------------------------------------------------------
+
+static std::string tune_signature(const dd_handle* h) {
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  unsigned long long hc = 1469598103934665603ull;   // FNV-1a over the cut points
+  auto mix = [&](long long v) { hc = (hc ^ (unsigned long long)v) * 1099511628211ull; };
+  for (int c : h->cuts_x) mix(c);
+  for (int c : h->cuts_y) mix(c + 1000003);
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%s N=%d px=%d py=%d cuts=%016llx ov=%d bc=%d prec=%d maxit=%d nrhs=%d m=%d",
+                prop.gcnArchName, h->n, h->p.px, h->p.py, hc, h->p.overlap, h->p.local_bc, h->prec, h->maxit,
+                h->nrhs, h->restart);
+  return buf;
+}
+
+static void invalidate_graph(dd_handle* h) {
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->graph_exec = nullptr;
+  h->graph = nullptr;
+}
+
+extern "C" dd_status dd_autotune(dd_handle* h, const char* cache_path, void* stream, char* report, int report_len) {
+  DD_TRY(check_handle(h));
+  hipStream_t st = (hipStream_t)stream;
+  const std::string sig = tune_signature(h);
+  std::string rep;
+  auto finish = [&](const std::string& how) -> dd_status {
+    char b[256];
+    std::snprintf(b, sizeof(b), "%s: inner_threads=%d lpt=%d dots_blocks=%d", how.c_str(), h->inner_nt,
+                  h->lpt ? 1 : 0, h->dots_blocks);
+    rep = std::string(b) + rep;
+    if (report && report_len > 0) {
+      std::snprintf(report, (size_t)report_len, "%s", rep.c_str());
+    }
+    invalidate_graph(h);
+    return DD_OK;
+  };
+  if (cache_path) {
+    FILE* fp = std::fopen(cache_path, "r");
+    if (fp) {
+      char line[1024];
+      while (std::fgets(line, sizeof(line), fp)) {
+        std::string l(line);
+        const size_t bar = l.find(" | ");
+        if (bar == std::string::npos || l.substr(0, bar) != sig) continue;
+        int nt = 0, lp = 1, db = 0;
+        if (std::sscanf(l.c_str() + bar + 3, "inner_threads=%d lpt=%d dots_blocks=%d", &nt, &lp, &db) == 3 &&
+            (nt == 256 || nt == 512)) {
+          h->inner_nt = nt;
+          h->lpt = lp != 0;
+          h->dots_blocks = db;
+          std::fclose(fp);
+          return finish("cache");
+        }
+      }
+      std::fclose(fp);
+    }
+  }
+  const int m = h->restart;
+  const long long nd = h->ndof;
+  const long long vstr = (long long)(m + 1) * nd, zstr = (long long)m * nd;
+  hipEvent_t e0, e1;
+  DD_HIP(hipEventCreate(&e0));
+  DD_HIP(hipEventCreate(&e1));
+  auto time_ms = [&](auto&& fn, int reps) -> double {
+    std::vector<float> t;
+    for (int r = 0; r < reps + 1; ++r) {
+      (void)hipEventRecord(e0, st);
+      fn();
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float x = 0.f;
+      (void)hipEventElapsedTime(&x, e0, e1);
+      if (r > 0) t.push_back(x);   // first run warms up
+    }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+  };
+  // representative data: pseudo-random residual in slot 0 (and basis vectors for the sweep)
+  const int jt = std::min(m - 1, 1024);
+  for (int q = 0; q < h->nrhs; ++q)
+    DD_HIP(ddh::launch_fill_hash(h->Vo + q * vstr, (long long)(jt + 2) * nd, 17081ull + q, st));
+  double best = 1e300;
+  int best_nt = h->inner_nt;
+  bool best_lpt = h->lpt;
+  char line[160];
+  for (int nt : {512, 256}) {
+    for (bool lp : {true, false}) {
+      h->inner_nt = nt;
+      h->lpt = lp;
+      dd_status s = DD_OK;
+      const double ms = time_ms([&]() { s = run_apply(h, h->Vo, vstr, h->Zo, zstr, nullptr, st); }, 3);
+      if (s != DD_OK) return s;
+      std::snprintf(line, sizeof(line), "\n  inner_threads=%d lpt=%d: %.3f ms per preconditioner application", nt,
+                    lp ? 1 : 0, ms);
+      rep += line;
+      if (ms < best) { best = ms; best_nt = nt; best_lpt = lp; }
+    }
+  }
+  h->inner_nt = best_nt;
+  h->lpt = best_lpt;
+  double bestd = 1e300;
+  int best_db = 0;
+  // the sweep's cost grows with the basis: time it at a short and a long basis
+  const int jshort = std::max(1, jt / 4);
+  for (int db : {1024, 2048, 4096, 8192, 16384}) {
+    const double ms = time_ms([&]() {
+      for (int jj : {jshort, jt})
+        (void)ddh::launch_dots2(h->Vo, vstr, h->Vo + (long long)jj * nd, vstr, h->Vo + (long long)(jj + 1) * nd, vstr,
+                                nd, ddh::host_step(jj), 1, jj, h->part, h->pstride, h->nrhs, nullptr, st, db);
+    }, 3);
+    std::snprintf(line, sizeof(line), "\n  dots_blocks=%d: %.3f ms for dot sweeps over %d and %d vectors", db, ms,
+                  jshort, jt);
+    rep += line;
+    if (ms < bestd) { bestd = ms; best_db = db; }
+  }
+  h->dots_blocks = best_db;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  DD_HIP(hipGetLastError());
+  if (cache_path) {
+    FILE* fp = std::fopen(cache_path, "a");
+    if (fp) {
+      std::fprintf(fp, "%s | inner_threads=%d lpt=%d dots_blocks=%d\n", sig.c_str(), h->inner_nt, h->lpt ? 1 : 0,
+                   h->dots_blocks);
+      std::fclose(fp);
+    }
+  }
+  return finish("measured");
 }
 
 // ---- kernel-level entry points -----------------------------------------------------

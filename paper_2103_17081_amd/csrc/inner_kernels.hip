@@ -14,6 +14,8 @@
 //   stop when the least-squares residual estimate <= tol * ||P f||;
 //   x = x0 + V y,  u = x + Z E^{-1} Z^T (f - B x)   (so f - B u = P (f - B x));
 //   z(owned nodes of j) = u.
+#include <algorithm>
+
 #include "coarse.hpp"
 #include "kernels.hpp"
 #include "stencil.hpp"
@@ -260,6 +262,9 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   cplx<T>* V = a.V + fo * (maxit + 1);
   cplx<double>* R = a.R + (long long)sidx * maxit * maxit;
   const int ldg = a.cs.n - 1;
+  const long long jstep = a.jdev ? (long long)*a.jdev : 0;
+  const cplx<double>* __restrict__ rin = a.r ? a.r + jstep * a.rslot : nullptr;
+  cplx<double>* __restrict__ zout = a.z ? a.z + jstep * a.zslot : nullptr;
 
   build_class_table<T>(d.robin, a.cs.kh, a.cs.kh2, L.tab);
   stage_lower(d, a.Ec, L.lc);
@@ -269,9 +274,9 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   // 1 and would lose precision, or underflow, in complex64.
   double fn2 = 0.0;
   for (int n = tid; n < nj; n += NT) {
-    if (a.r) {
+    if (rin) {
       const int lj = n / nx, li = n - lj * nx;
-      fn2 += cabs2(a.r[(long long)rhs * a.rstride + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
+      fn2 += cabs2(rin[(long long)rhs * a.rstride + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
     } else {
       fn2 += cabs2(ccast<double>(F[n]));
     }
@@ -280,12 +285,12 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   const double fscale = fnorm > 0.0 ? 1.0 / fnorm : 0.0;
   // F holds the scaled right-hand side when gathered here; a caller-supplied F is
   // left untouched and scaled on use (fmul).
-  const T fmul = a.r ? T(1) : T(fscale);
+  const T fmul = rin ? T(1) : T(fscale);
   for (int n = tid; n < nj; n += NT) {
     cplx<T> v;
-    if (a.r) {
+    if (rin) {
       const int lj = n / nx, li = n - lj * nx;
-      v = ccast<T>(fscale * a.r[(long long)rhs * a.rstride + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
+      v = ccast<T>(fscale * rin[(long long)rhs * a.rstride + (long long)(d.j0 + lj - 1) * ldg + (d.i0 + li - 1)]);
       F[n] = v;
     } else {
       v = fmul * F[n];
@@ -461,10 +466,10 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
     const int lj = n / nx, li = n - lj * nx;
     const cplx<T> u = L.A[n] + ccast<T>(prolong_at(d, L.ca, li, lj));
     if (a.U) a.U[fo + n] = ccast<T>(fnorm * ccast<double>(u));
-    if (a.z) {
+    if (zout) {
       const int gi = d.i0 + li, gj = d.j0 + lj;
       if (gi >= d.oi0 && gi <= d.oi1 && gj >= d.oj0 && gj <= d.oj1)
-        a.z[(long long)rhs * a.zstride + (long long)(gj - 1) * ldg + (gi - 1)] = fnorm * ccast<double>(u);
+        zout[(long long)rhs * a.zstride + (long long)(gj - 1) * ldg + (gi - 1)] = fnorm * ccast<double>(u);
     }
   }
   if (tid == 0) {
@@ -488,19 +493,19 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
 
 template <typename T>
 size_t inner_lds_bytes(int max_nj, int max_nc, int maxit) {
-  return lds_bytes<T>(max_nj, max_nc, maxit, kInnerThreads);
+  return std::max(lds_bytes<T>(max_nj, max_nc, maxit, kInnerThreads), lds_bytes<T>(max_nj, max_nc, maxit, 256));
 }
 
 template <typename T>
 hipError_t launch_inner_solve(const InnerArgs<T>& a, hipStream_t st) {
-  const size_t lds = lds_bytes<T>(a.max_nj, a.max_nc, a.maxit, kInnerThreads);
   const int nblocks = a.cs.nsub * a.nrhs;
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)inner_solve_kernel<T, kInnerThreads>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  if (a.nt == 256) {
+    const size_t lds = lds_bytes<T>(a.max_nj, a.max_nc, a.maxit, 256);
+    hipLaunchKernelGGL((inner_solve_kernel<T, 256>), dim3(nblocks), dim3(256), lds, st, a);
+  } else {
+    const size_t lds = lds_bytes<T>(a.max_nj, a.max_nc, a.maxit, kInnerThreads);
+    hipLaunchKernelGGL((inner_solve_kernel<T, kInnerThreads>), dim3(nblocks), dim3(kInnerThreads), lds, st, a);
   }
-  hipLaunchKernelGGL((inner_solve_kernel<T, kInnerThreads>), dim3(nblocks), dim3(kInnerThreads), lds, st, a);
   return hipGetLastError();
 }
 
@@ -552,11 +557,6 @@ hipError_t launch_deflated_apply(const SubDesc* subs, int nsub, Consts cs, int, 
                                  const cplx<double>* Ec, const cplx<T>* v, cplx<T>* w, int max_nj, int max_nc,
                                  hipStream_t st) {
   const size_t lds = lds_bytes<T>(max_nj, max_nc, 1, kBlock);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)deflated_apply_kernel<T>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(deflated_apply_kernel<T>, dim3(nsub), dim3(kBlock), lds, st, subs, cs, fac, Ec, v, w,
                      max_nj, max_nc);
   return hipGetLastError();
@@ -656,8 +656,27 @@ hipError_t launch_scatter(const SubDesc* subs, int nsub, Consts cs, const cplx<T
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t configure_inner(int max_nj, int max_nc, int maxit) {
+  const size_t lds = lds_bytes<T>(max_nj, max_nc, maxit, kInnerThreads);
+  hipError_t e = hipSuccess;
+  if (lds > 65536)
+    e = hipFuncSetAttribute((const void*)inner_solve_kernel<T, kInnerThreads>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const size_t lds256 = lds_bytes<T>(max_nj, max_nc, maxit, 256);
+  if (e == hipSuccess && lds256 > 65536)
+    e = hipFuncSetAttribute((const void*)inner_solve_kernel<T, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds256);
+  const size_t lds2 = lds_bytes<T>(max_nj, max_nc, 1, kBlock);
+  if (e == hipSuccess && lds2 > 65536)
+    e = hipFuncSetAttribute((const void*)deflated_apply_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds2);
+  return e;
+}
+
 #define DDH_INSTANTIATE(T)                                                                                   \
   template hipError_t launch_inner_solve<T>(const InnerArgs<T>&, hipStream_t);                                \
+  template hipError_t configure_inner<T>(int, int, int);                                                     \
   template size_t inner_lds_bytes<T>(int, int, int);                                                          \
   template hipError_t launch_local_apply<T>(const SubDesc*, int, Consts, int, const cplx<T>*, cplx<T>*, int,  \
                                             hipStream_t);                                                     \

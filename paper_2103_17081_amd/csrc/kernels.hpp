@@ -39,12 +39,19 @@ struct InnerArgs {
                                  //     algorithmic bytes
   long long nfine, ndof;
   long long rstride, zstride;    // per right-hand side strides of r and z (elements)
+  const int* jdev;               // if set: r and z are advanced by (*jdev) * rslot / zslot
+  long long rslot, zslot;        // (graph-captured outer steps read the step index on the device)
   int nrhs, maxit, max_nj, max_nc;
   double tol;
+  int nt;                        // threads per workgroup: 256 or 512 (autotuned)
 };
 
 template <typename T>
 hipError_t launch_inner_solve(const InnerArgs<T>& a, hipStream_t st);
+// Raise the dynamic-LDS limit of the subdomain kernels once, at set-up (not while a
+// stream is being captured).
+template <typename T>
+hipError_t configure_inner(int max_nj, int max_nc, int maxit);
 template <typename T>
 size_t inner_lds_bytes(int max_nj, int max_nc, int maxit);
 

@@ -4,6 +4,8 @@
 //
 // Vectors: [nrhs][ndof] complex<double>, interior nodes x fastest.  Bases:
 // basis(rhs, i) = base + (rhs * nvec + i) * ndof.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "outer.hpp"
 
@@ -13,9 +15,13 @@ namespace ddh {
 // NE/SW -kh2/12), Dirichlet neighbours eliminated.
 __global__ void __launch_bounds__(256) global_apply_kernel(Consts cs, const cplx<double>* __restrict__ v,
                                                             long long vstride, cplx<double>* __restrict__ w,
-                                                            long long wstride, const int* __restrict__ done) {
+                                                            long long wstride, const int* __restrict__ done,
+                                                            StepRef sr, long long vslot, long long wslot) {
   const int rhs = blockIdx.z;
   if (done && done[rhs]) return;
+  const long long jj = sr.get();
+  v += jj * vslot;
+  w += jj * wslot;
   const int m = cs.n - 1;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -42,11 +48,22 @@ hipError_t launch_global_apply(Consts cs, const cplx<double>* v, cplx<double>* w
 }
 
 hipError_t launch_global_apply_masked(Consts cs, const cplx<double>* v, long long vstride, cplx<double>* w,
-                                      long long wstride, int nrhs, const int* done, hipStream_t st) {
+                                      long long wstride, int nrhs, const int* done, hipStream_t st, StepRef sr,
+                                      long long vslot, long long wslot) {
   const int m = cs.n - 1;
   dim3 blk(64, 4);
   dim3 grd((m + 63) / 64, (m + 3) / 4, nrhs);
-  hipLaunchKernelGGL(global_apply_kernel, grd, blk, 0, st, cs, v, vstride, w, wstride, done);
+  hipLaunchKernelGGL(global_apply_kernel, grd, blk, 0, st, cs, v, vstride, w, wstride, done, sr, vslot, wslot);
+  return hipGetLastError();
+}
+
+// Advance the device-side outer step index (one thread).
+__global__ void advance_step_kernel(int* jdev) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) jdev[0] += 1;
+}
+
+hipError_t launch_advance_step(int* jdev, hipStream_t st) {
+  hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, jdev);
   return hipGetLastError();
 }
 
@@ -122,104 +139,130 @@ __global__ void __launch_bounds__(256) dots_kernel(const cplx<double>* __restric
 // Delayed CGS2 pass 1: one sweep over the basis for two vectors.  Slots:
 // [0, nvec): conj(V_i) . x1;  [nvec, 2 nvec): conj(V_i) . x2 (if x2);
 // 2 nvec: |x1|^2;  2 nvec + 1: conj(x1) . x2;  2 nvec + 2: |x2|^2.
-// Each block covers kChunkRows rows and kVecsPerBlock basis vectors (the last group
-// also produces the three self slots); all loads of a vector group are issued before
-// the products are formed.
+// Work items are (row chunk of kChunkRows rows, group of kVecsPerBlock basis vectors);
+// the last group also produces the three self slots.  Blocks stride over the items,
+// so the grid is fixed while nvec grows; all loads of an item are issued before the
+// products are formed.  With `sr.jdev` set, nvec = *jdev and x1, x2 are basis
+// vectors nvec and nvec+1 (graph-captured steps); otherwise nvec = sr.jhost and
+// x1, x2 are the given vectors.
 __global__ void __launch_bounds__(256) dots2_kernel(const cplx<double>* __restrict__ basis, long long bstride,
                                                     const cplx<double>* __restrict__ x1, long long x1stride,
                                                     const cplx<double>* __restrict__ x2, long long x2stride,
-                                                    long long ndof, int nvec, cplx<double>* __restrict__ part,
-                                                    int pstride, const int* __restrict__ done) {
+                                                    long long ndof, StepRef sr, int two_in,
+                                                    cplx<double>* __restrict__ part, int pstride,
+                                                    const int* __restrict__ done) {
   const int rhs = blockIdx.z;
   if (done && done[rhs]) return;
   __shared__ cplx<double> red[4][2 * kVecsPerBlock + 3];
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-  const int nchunk = gridDim.x;
-  const long long n0 = (long long)blockIdx.x * kChunkRows + tid;
-  const bool two = x2 != nullptr;
+  const int nvec = sr.get();
+  const bool two = two_in != 0;
+  const cplx<double>* X1 = sr.jdev ? basis + rhs * bstride + (long long)nvec * ndof : x1 + rhs * x1stride;
+  const cplx<double>* X2 = sr.jdev ? basis + rhs * bstride + (long long)(nvec + 1) * ndof
+                                   : (two ? x2 + rhs * x2stride : nullptr);
+  const int nchunk = (int)((ndof + kChunkRows - 1) / kChunkRows);
+  const int ngroups = nvec > 0 ? (nvec + kVecsPerBlock - 1) / kVecsPerBlock : 1;
+  const long long items = (long long)nchunk * ngroups;
+  // contiguous, chunk-major item range: consecutive items share a row chunk, so x1, x2
+  // are loaded once per chunk change rather than once per item
+  const long long lo = items * blockIdx.x / gridDim.x, hi = items * (blockIdx.x + 1) / gridDim.x;
+  int cur = -1;
   cplx<double> a[kRowsPerThread], b[kRowsPerThread];
-#pragma unroll
-  for (int r = 0; r < kRowsPerThread; ++r) {
-    const long long n = n0 + r * 256;
-    a[r] = n < ndof ? x1[rhs * x1stride + n] : czero<double>();
-    b[r] = (two && n < ndof) ? x2[rhs * x2stride + n] : czero<double>();
-  }
-  const int s0 = blockIdx.y * kVecsPerBlock;
-  const int s1 = min(nvec, s0 + kVecsPerBlock);
-  const int cnt = s1 > s0 ? s1 - s0 : 0;
-  cplx<double> v[kVecsPerBlock][kRowsPerThread];
-#pragma unroll
-  for (int q = 0; q < kVecsPerBlock; ++q) {
-#pragma unroll
-    for (int r = 0; r < kRowsPerThread; ++r) {
-      const long long n = n0 + r * 256;
-      v[q][r] = (q < cnt && n < ndof) ? basis[rhs * bstride + (long long)(s0 + q) * ndof + n] : czero<double>();
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < kVecsPerBlock; ++q) {
-    if (q < cnt) {
-      cplx<double> p1 = czero<double>(), p2 = czero<double>();
+  for (long long item = lo; item < hi; ++item) {
+    const int chunk = (int)(item / ngroups), group = (int)(item % ngroups);
+    const long long n0 = (long long)chunk * kChunkRows + tid;
+    if (chunk != cur) {
+      cur = chunk;
 #pragma unroll
       for (int r = 0; r < kRowsPerThread; ++r) {
-        p1 = p1 + cmulc(v[q][r], a[r]);
-        if (two) p2 = p2 + cmulc(v[q][r], b[r]);
-      }
-      p1.re = wave_sum(p1.re); p1.im = wave_sum(p1.im);
-      if (lane == 0) red[wave][q] = p1;
-      if (two) {
-        p2.re = wave_sum(p2.re); p2.im = wave_sum(p2.im);
-        if (lane == 0) red[wave][kVecsPerBlock + q] = p2;
+        const long long n = n0 + r * 256;
+        a[r] = n < ndof ? X1[n] : czero<double>();
+        b[r] = (two && n < ndof) ? X2[n] : czero<double>();
       }
     }
-  }
-  const bool self = blockIdx.y == gridDim.y - 1;
-  if (self) {
-    cplx<double> p[3] = {czero<double>(), czero<double>(), czero<double>()};
+    const int s0 = group * kVecsPerBlock;
+    const int s1 = min(nvec, s0 + kVecsPerBlock);
+    const int cnt = s1 > s0 ? s1 - s0 : 0;
+    cplx<double> v[kVecsPerBlock][kRowsPerThread];
 #pragma unroll
-    for (int r = 0; r < kRowsPerThread; ++r) {
-      p[0].re += cabs2(a[r]);
-      p[1] = p[1] + cmulc(a[r], b[r]);
-      p[2].re += cabs2(b[r]);
+    for (int q = 0; q < kVecsPerBlock; ++q) {
+#pragma unroll
+      for (int r = 0; r < kRowsPerThread; ++r) {
+        const long long n = n0 + r * 256;
+        v[q][r] = (q < cnt && n < ndof) ? basis[rhs * bstride + (long long)(s0 + q) * ndof + n] : czero<double>();
+      }
     }
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      p[e].re = wave_sum(p[e].re); p[e].im = wave_sum(p[e].im);
-      if (lane == 0) red[wave][2 * kVecsPerBlock + e] = p[e];
+    for (int q = 0; q < kVecsPerBlock; ++q) {
+      if (q < cnt) {
+        cplx<double> p1 = czero<double>(), p2 = czero<double>();
+#pragma unroll
+        for (int r = 0; r < kRowsPerThread; ++r) {
+          p1 = p1 + cmulc(v[q][r], a[r]);
+          if (two) p2 = p2 + cmulc(v[q][r], b[r]);
+        }
+        p1.re = wave_sum(p1.re); p1.im = wave_sum(p1.im);
+        if (lane == 0) red[wave][q] = p1;
+        if (two) {
+          p2.re = wave_sum(p2.re); p2.im = wave_sum(p2.im);
+          if (lane == 0) red[wave][kVecsPerBlock + q] = p2;
+        }
+      }
     }
-  }
-  __syncthreads();
-  if (tid < 2 * kVecsPerBlock + 3) {
-    int slot = -1;
-    if (tid < kVecsPerBlock) slot = tid < cnt ? s0 + tid : -1;
-    else if (tid < 2 * kVecsPerBlock) slot = (two && tid - kVecsPerBlock < cnt) ? nvec + s0 + tid - kVecsPerBlock : -1;
-    else slot = self ? 2 * nvec + (tid - 2 * kVecsPerBlock) : -1;
-    if (slot >= 0) {
-      const cplx<double> t = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-      part[((long long)rhs * pstride + slot) * nchunk + blockIdx.x] = t;
+    const bool self = group == ngroups - 1;
+    if (self) {
+      cplx<double> p[3] = {czero<double>(), czero<double>(), czero<double>()};
+#pragma unroll
+      for (int r = 0; r < kRowsPerThread; ++r) {
+        p[0].re += cabs2(a[r]);
+        p[1] = p[1] + cmulc(a[r], b[r]);
+        p[2].re += cabs2(b[r]);
+      }
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        p[e].re = wave_sum(p[e].re); p[e].im = wave_sum(p[e].im);
+        if (lane == 0) red[wave][2 * kVecsPerBlock + e] = p[e];
+      }
     }
+    __syncthreads();
+    if (tid < 2 * kVecsPerBlock + 3) {
+      int slot = -1;
+      if (tid < kVecsPerBlock) slot = tid < cnt ? s0 + tid : -1;
+      else if (tid < 2 * kVecsPerBlock) slot = (two && tid - kVecsPerBlock < cnt) ? nvec + s0 + tid - kVecsPerBlock : -1;
+      else slot = self ? 2 * nvec + (tid - 2 * kVecsPerBlock) : -1;
+      if (slot >= 0) {
+        const cplx<double> t = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+        part[((long long)rhs * pstride + slot) * nchunk + chunk] = t;
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Stage 2: out[rhs][s] = sum over chunks; mode 0: H[s] = out, 1: H[s] += out, 2: none.
-// One wavefront per (slot, rhs).
+// Stage 2: out[rhs][s] = sum over chunks for s < nslots = mul * j + add (j from the
+// StepRef); mode 0: H[s] = out, 1: H[s] += out, 2: none.  One wavefront per slot,
+// striding over the slots.
 __global__ void __launch_bounds__(64) reduce_parts_kernel(const cplx<double>* __restrict__ part, int nchunk,
-                                                          int pstride, cplx<double>* __restrict__ out, int ostride,
+                                                          int pstride, StepRef sr, int mul, int add,
+                                                          cplx<double>* __restrict__ out, int ostride,
                                                           cplx<double>* __restrict__ H, int hstride, int mode,
                                                           const int* __restrict__ done) {
-  const int s = blockIdx.x, rhs = blockIdx.y;
+  const int rhs = blockIdx.y;
   if (done && done[rhs]) return;
-  const cplx<double>* p = part + ((long long)rhs * pstride + s) * nchunk;
-  cplx<double> acc = czero<double>();
-  for (int c = threadIdx.x; c < nchunk; c += 64) acc = acc + p[c];
-  acc.re = wave_sum(acc.re);
-  acc.im = wave_sum(acc.im);
-  if (threadIdx.x == 0) {
-    out[rhs * ostride + s] = acc;
-    if (H) {
-      cplx<double>* hh = H + (long long)rhs * hstride + s;
-      if (mode == 0) *hh = acc;
-      else if (mode == 1) *hh = *hh + acc;
+  const int nslots = mul * sr.get() + add;
+  for (int s = blockIdx.x; s < nslots; s += gridDim.x) {
+    const cplx<double>* p = part + ((long long)rhs * pstride + s) * nchunk;
+    cplx<double> acc = czero<double>();
+    for (int c = threadIdx.x; c < nchunk; c += 64) acc = acc + p[c];
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (threadIdx.x == 0) {
+      out[rhs * ostride + s] = acc;
+      if (H) {
+        cplx<double>* hh = H + (long long)rhs * hstride + s;
+        if (mode == 0) *hh = acc;
+        else if (mode == 1) *hh = *hh + acc;
+      }
     }
   }
 }
@@ -279,12 +322,14 @@ __global__ void __launch_bounds__(256) update_kernel(const cplx<double>* __restr
 // coefficient vectors a = s / alpha and b = c - s h_jj / alpha and the scalars
 // (1/alpha, h_jj/alpha, 1/gamma) come from dcgs2_step_kernel.
 __global__ void __launch_bounds__(256) dcgs2_update_kernel(cplx<double>* __restrict__ basis, long long bstride,
-                                                           long long ndof, int j, const cplx<double>* __restrict__ ca,
+                                                           long long ndof, StepRef sr,
+                                                           const cplx<double>* __restrict__ ca,
                                                            const cplx<double>* __restrict__ cb, int cstride,
                                                            const cplx<double>* __restrict__ scal,
                                                            const int* __restrict__ done) {
   const int rhs = blockIdx.y;
   if (done && done[rhs]) return;
+  const int j = sr.get();
   __shared__ cplx<double> la[kOuterMaxDots], lb[kOuterMaxDots];
   cplx<double>* V = basis + rhs * bstride;
   const long long n0 = (long long)blockIdx.x * kChunkRows + threadIdx.x;
@@ -348,12 +393,19 @@ __global__ void __launch_bounds__(256) dcgs2_update_kernel(cplx<double>* __restr
 //   gamma_{j+1} = sqrt(ww - |c|^2 - |h_jj|^2) (Pythagoras; only a scaling that the next
 //   step corrects exactly through nu).
 // Step 0 has no column to finalise; it sets g_0 = beta * alpha.
-__global__ void __launch_bounds__(256) dcgs2_step_kernel(OuterState st, int j, const cplx<double>* __restrict__ dots,
-                                                         int dstride, int has_w, cplx<double>* __restrict__ ca,
-                                                         cplx<double>* __restrict__ cb, int cstride,
-                                                         cplx<double>* __restrict__ scal) {
+__global__ void __launch_bounds__(256) dcgs2_step_kernel(OuterState st, StepRef sr, long long ndof,
+                                                         const cplx<double>* __restrict__ dots, int dstride, int has_w,
+                                                         cplx<double>* __restrict__ ca, cplx<double>* __restrict__ cb,
+                                                         int cstride, cplx<double>* __restrict__ scal) {
   const int rhs = blockIdx.x;
   if (st.done[rhs]) return;
+  const int j = sr.get();
+  if (threadIdx.x == 0 && has_w) {
+    // one preconditioner application and the two basis sweeps of this step
+    st.applies[rhs] += 1;
+    atomicAdd(st.sweep_bytes + 0, 16ull * (unsigned long long)ndof * (unsigned long long)(j + 2));
+    atomicAdd(st.sweep_bytes + 1, 16ull * (unsigned long long)ndof * (unsigned long long)(j + 4));
+  }
   extern __shared__ __align__(16) unsigned char gsm[];
   const int m = st.restart;
   cplx<double>* lcol = (cplx<double>*)gsm;          // j + 1 entries
@@ -589,6 +641,34 @@ __global__ void cycle_init_kernel(OuterState st, int nrhs) {
 
 int outer_chunks(long long ndof) { return (int)((ndof + kChunkRows - 1) / kChunkRows); }
 
+// Deterministic pseudo-random fill (a 64-bit mix of the index and seed mapped to
+// [-1, 1)), used only to give the autotuner representative data.
+__global__ void fill_hash_kernel(cplx<double>* __restrict__ x, long long n, unsigned long long seed) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    unsigned long long z = (unsigned long long)i * 0x9E3779B97F4A7C15ull + seed;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = cplx<double>{(double)(z & 0xffffffffull) / 2147483648.0 - 1.0, (double)(z >> 32) / 2147483648.0 - 1.0};
+  }
+}
+
+hipError_t launch_fill_hash(cplx<double>* x, long long n, unsigned long long seed, hipStream_t st) {
+  hipLaunchKernelGGL(fill_hash_kernel, dim3(2048), dim3(256), 0, st, x, n, seed);
+  return hipGetLastError();
+}
+
+hipError_t configure_outer() {
+  const int lds = (int)((size_t)(kGivensMax + 2) * 40);
+  hipError_t e = hipFuncSetAttribute((const void*)dcgs2_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)givens_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return e;
+}
+
+
+constexpr int kMaxSweepBlocks = 4096;   // grid cap of the striding outer sweeps
+
 hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<double>* w, long long wstride,
                        long long ndof, int nvec, int with_norm, cplx<double>* part, int pstride, int nrhs,
                        const int* done, hipStream_t st) {
@@ -599,11 +679,12 @@ hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_parts(const cplx<double>* part, long long ndof, int pstride, int nslots,
-                               cplx<double>* out, int ostride, cplx<double>* H, int hstride, int mode, int nrhs,
-                               const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(nslots, nrhs), dim3(64), 0, st, part, outer_chunks(ndof), pstride,
-                     out, ostride, H, hstride, mode, done);
+hipError_t launch_reduce_parts(const cplx<double>* part, long long ndof, int pstride, StepRef sr, int mul, int add,
+                               int jmax, cplx<double>* out, int ostride, cplx<double>* H, int hstride, int mode,
+                               int nrhs, const int* done, hipStream_t st) {
+  const int grid = std::min(mul * jmax + add, 1024);
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid, nrhs), dim3(64), 0, st, part, outer_chunks(ndof), pstride, sr,
+                     mul, add, out, ostride, H, hstride, mode, done);
   return hipGetLastError();
 }
 
@@ -624,36 +705,32 @@ hipError_t launch_scale(const cplx<double>* w, long long wstride, cplx<double>* 
 }
 
 hipError_t launch_dots2(const cplx<double>* basis, long long bstride, const cplx<double>* x1, long long x1stride,
-                        const cplx<double>* x2, long long x2stride, long long ndof, int nvec, cplx<double>* part,
-                        int pstride, int nrhs, const int* done, hipStream_t st) {
-  const int groups = nvec > 0 ? (nvec + kVecsPerBlock - 1) / kVecsPerBlock : 1;
-  dim3 grid(outer_chunks(ndof), groups, nrhs);
-  hipLaunchKernelGGL(dots2_kernel, grid, dim3(256), 0, st, basis, bstride, x1, x1stride, x2, x2stride, ndof, nvec,
-                     part, pstride, done);
+                        const cplx<double>* x2, long long x2stride, long long ndof, StepRef sr, int two, int jmax,
+                        cplx<double>* part, int pstride, int nrhs, const int* done, hipStream_t st, int max_blocks) {
+  const int groups = jmax > 0 ? (jmax + kVecsPerBlock - 1) / kVecsPerBlock : 1;
+  const long long items = (long long)outer_chunks(ndof) * groups;
+  const int grid = (int)std::min<long long>(items, max_blocks > 0 ? max_blocks : kMaxSweepBlocks);
+  // (each workgroup takes a contiguous range of about items / grid items)
+  hipLaunchKernelGGL(dots2_kernel, dim3(grid, 1, nrhs), dim3(256), 0, st, basis, bstride, x1, x1stride, x2, x2stride,
+                     ndof, sr, two, part, pstride, done);
   return hipGetLastError();
 }
 
-hipError_t launch_dcgs2_step(const OuterState& s, int j, const cplx<double>* dots, int dstride, int has_w,
-                             cplx<double>* ca, cplx<double>* cb, int cstride, cplx<double>* scal, int nrhs,
-                             hipStream_t st) {
-  if (j > kGivensMax) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(j + 2) * sizeof(cplx<double>) + (size_t)(j + 1) * (sizeof(cplx<double>) + sizeof(double));
-  static bool attr = false;
-  if (!attr && lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)dcgs2_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)((size_t)(kGivensMax + 2) * 40));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL(dcgs2_step_kernel, dim3(nrhs), dim3(256), lds, st, s, j, dots, dstride, has_w, ca, cb, cstride,
-                     scal);
+hipError_t launch_dcgs2_step(const OuterState& s, StepRef sr, int jmax, long long ndof, const cplx<double>* dots,
+                             int dstride, int has_w, cplx<double>* ca, cplx<double>* cb, int cstride,
+                             cplx<double>* scal, int nrhs, hipStream_t st) {
+  if (jmax > kGivensMax) return hipErrorInvalidValue;
+  const size_t lds =
+      (size_t)(jmax + 2) * sizeof(cplx<double>) + (size_t)(jmax + 1) * (sizeof(cplx<double>) + sizeof(double));
+  hipLaunchKernelGGL(dcgs2_step_kernel, dim3(nrhs), dim3(256), lds, st, s, sr, ndof, dots, dstride, has_w, ca, cb,
+                     cstride, scal);
   return hipGetLastError();
 }
 
-hipError_t launch_dcgs2_update(cplx<double>* basis, long long bstride, long long ndof, int j, const cplx<double>* ca,
-                               const cplx<double>* cb, int cstride, const cplx<double>* scal, int nrhs,
-                               const int* done, hipStream_t st) {
-  hipLaunchKernelGGL(dcgs2_update_kernel, dim3(outer_chunks(ndof), nrhs), dim3(256), 0, st, basis, bstride, ndof, j,
+hipError_t launch_dcgs2_update(cplx<double>* basis, long long bstride, long long ndof, StepRef sr,
+                               const cplx<double>* ca, const cplx<double>* cb, int cstride, const cplx<double>* scal,
+                               int nrhs, const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(dcgs2_update_kernel, dim3(outer_chunks(ndof), nrhs), dim3(256), 0, st, basis, bstride, ndof, sr,
                      ca, cb, cstride, scal, done);
   return hipGetLastError();
 }
@@ -661,13 +738,6 @@ hipError_t launch_dcgs2_update(cplx<double>* basis, long long bstride, long long
 hipError_t launch_givens(const OuterState& s, int j, int nrhs, hipStream_t st) {
   if (j + 1 > kGivensMax) return hipErrorInvalidValue;
   const size_t lds = (size_t)(j + 2) * sizeof(cplx<double>) + (size_t)(j + 1) * (sizeof(cplx<double>) + sizeof(double));
-  static bool attr = false;
-  if (!attr && lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)givens_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)((size_t)(kGivensMax + 2) * 40));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
   hipLaunchKernelGGL(givens_kernel, dim3(nrhs), dim3(256), lds, st, s, j);
   return hipGetLastError();
 }

@@ -170,3 +170,47 @@ def test_zero_rhs_solve(torch):
         u, st = gpu.solve(f)
         assert st["outer_iters"] == 0 and st["status"] == "DD_OK"
         assert int(torch.count_nonzero(u)) == 0
+
+
+@pytest.mark.parametrize("name,prec", [("small", 64), ("small", 32), ("medium", 32)])
+def test_graph_replay_matches_eager(torch, name, prec):
+    """Outer steps replayed from the captured graph give bit-identical results to the same
+    kernels launched one by one, on repeated solves with eager work in between."""
+    _case("graph vs eager", name, prec)
+    w, S = oracle_for(name)
+    f = to_gpu(torch, w.rhs[0])
+    with solver_for(name, precision=prec, use_graph=False) as eager:
+        ue, se = eager.solve(f)
+        ue = to_np(ue)
+    with solver_for(name, precision=prec, use_graph=True, graph_steps=8) as g:
+        for rep in range(3):
+            ug, sg = g.solve(f)
+            ug = to_np(ug)
+            _ = g.op_global_apply(f)          # eager work between replays
+            torch.cuda.synchronize()
+            assert sg["graph_replays"] > 0
+            assert sg["outer_iters"] == se["outer_iters"], (rep, sg["outer_iters"], se["outer_iters"])
+            assert sg["inner_iters_total"] == se["inner_iters_total"]
+            assert np.array_equal(ug, ue), rep
+
+
+def test_autotune_and_cache(torch, tmp_path):
+    """The autotuner measures, records its choice in the cache, reloads it, and the tuned
+    solver still matches the oracle's outer count."""
+    _case("autotune")
+    gold = _golden()["small"]
+    w, S = oracle_for("small")
+    cache = str(tmp_path / "tune.txt")
+    with solver_for("small", precision=64) as g:
+        rep = g.autotune(cache)
+        assert rep.startswith("measured"), rep
+        assert "inner_threads=" in rep and "dots_blocks=" in rep
+        lines = open(cache).read().strip().splitlines()
+        assert len(lines) == 1 and " | inner_threads=" in lines[0]
+        u, st = g.solve(to_gpu(torch, w.rhs[0]))
+        rel = np.linalg.norm(w.rhs[0] - S.A @ to_np(u)) / np.linalg.norm(w.rhs[0])
+        assert rel <= 1e-6 and abs(st["outer_iters"] - gold["outer_iters"]) <= 1
+    with solver_for("small", precision=64) as g2:
+        rep2 = g2.autotune(cache)
+        assert rep2.startswith("cache"), rep2
+        assert rep2.split("\n")[0].split(": ", 1)[1] == rep.split("\n")[0].split(": ", 1)[1]
