@@ -111,6 +111,8 @@ typedef struct {
   int timed_steps;             /* outer steps launched one by one; the per-phase times above cover
                                   only these (events cannot be timed inside graph replays) */
   double ms_steps;             /* all outer steps, from events around each replay or batch */
+  double ms_guess;             /* network input tiles + forward pass of an attached guess network
+                                  (timed outer steps only; 0 without a network) */
 } dd_stats;
 
 /* Fill *p with the defaults: k = 20, ppwl = 10, 2 x 2 uniform subdomains, overlap 1,
@@ -189,6 +191,93 @@ dd_status dd_op_scatter(dd_handle* h, int precision, const void* u, void* z, voi
    iteration counts and flags (bit 0 guess accepted, bit 1 not converged). */
 dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void* u, int32_t* iters,
                             int32_t* flags, void* stream);
+
+/* ---- learned initial guess ---------------------------------------------------------
+ * The paper's subdomain GMRES starts from zero (Sec. 3).  A guess network maps the
+ * right-hand side of a subdomain solve to a starting vector; the solve keeps it only
+ * when it lowers the deflated residual, ||P_j (f_j - B_j g)|| < ||P_j f_j|| (Sec. 2,
+ * eq. 4), and otherwise starts from zero, so the stopping test (relative to
+ * ||P_j f_j||) and the preconditioner's definition are unchanged.
+ *
+ * Network: a convolutional encoder-decoder on T x T tiles (subdomain tile at the tile
+ * origin, zero padding), bf16 weights and activations with fp32 accumulation.
+ *   a1 = relu(conv(x)) [c1, T]        a5 = relu(conv(cat(up(a4), a3))) [c2, T/4]
+ *   a2 = relu(conv(pool(a1))) [c2, T/2]  a6 = relu(conv(cat(up(a5), a2))) [c1, T/2]
+ *   a3 = relu(conv(pool(a2))) [c3, T/4]  a7 = relu(conv(cat(up(a6), a1))) [c1, T]
+ *   a4 = relu(conv(pool(a3))) [c4, T/8]  y  = a7 W8 + b8  (1x1, 2 channels)
+ * conv = 3x3, zero padding; pool = 2x2 average; up = 2x nearest; cat = channels, first
+ * operand first.  Flat parameters (fp32): W1, b1, ..., W8, b8, each C-ordered, a 3x3
+ * weight indexed [ky][kx][cin][cout].
+ * Tiles are NHWC fp32.  Input channels: Re f, Im f times s = sqrt(n_j) / ||f_j||, the
+ * constant k h, and a mask (1 on nodes, -1 on nodes of an impedance side); 0 outside
+ * the subdomain.  Output: Re, Im of s u in the same scaling.  Tile b of a handle's
+ * batch is right-hand side b / nsub, subdomain b % nsub.
+ */
+typedef struct dd_net dd_net;
+
+typedef struct {
+  int widths[4];               /* c1..c4, multiples of 16, c1 <= 64 (default 16, 32, 64, 64) */
+  int tile;                    /* T: 32, 64 or 128 */
+  int max_batch;               /* tiles per call */
+  int train;                   /* 1: also allocate gradient and optimiser state */
+  unsigned long long seed;     /* He-normal initial weights from this seed, zero biases */
+} dd_net_params;
+
+/* Per-tile operator description for the training loss: nx, ny of the subdomain tile;
+   edges: bit s set when side s (0 left, 1 right, 2 bottom, 3 top) of the tile is an
+   edge of the subdomain's cells; robin: bit s set when side s carries the impedance
+   condition; kh = k h. */
+typedef struct {
+  int nx, ny, edges, robin;
+  double kh;
+} dd_tile_desc;
+
+void dd_net_default_params(dd_net_params* p);
+/* Allocate a network and its device workspaces.  DD_EINVAL for unsupported sizes. */
+dd_status dd_net_create(const dd_net_params* p, dd_net** out);
+dd_status dd_net_destroy(dd_net* net);
+int64_t dd_net_num_params(const dd_net* net);
+/* Host fp32 parameter vector in, or out (n must equal dd_net_num_params).  Setting
+   parameters resets the optimiser state.  Both synchronise the default stream. */
+dd_status dd_net_set_params(dd_net* net, const float* host, int64_t n);
+dd_status dd_net_get_params(const dd_net* net, float* host, int64_t n);
+/* y = network(x) for `batch` tiles: x device fp32 [batch][T][T][4], y device fp32
+   [batch][T][T][2]. */
+dd_status dd_net_forward(dd_net* net, const float* x, int batch, float* y, void* stream);
+/* Training loss and its gradient (network built with train = 1).  x as above, t device
+   fp32 [batch][T][T][2] (target s u), desc host [batch].  With e = m (y - t) on the tile's
+   nodes and B the tile's subdomain operator (Sec. 2, eq. 2, impedance rows per desc):
+     loss = mean_b ( w_res ||B e||^2 / ||B t||^2 + w_err ||e||^2 / ||t||^2 ).
+   grad (device fp32 [num_params], may be NULL) receives dloss/dparams, which also stays
+   in the network for dd_net_adam; *loss (host, may be NULL) the loss.  Synchronises
+   `stream`. */
+dd_status dd_net_gradient(dd_net* net, const float* x, const float* t, const dd_tile_desc* desc, int batch,
+                          double w_res, double w_err, float* grad, double* loss, void* stream);
+/* One Adam step (Kingma and Ba, 2015) with the last gradient. */
+dd_status dd_net_adam(dd_net* net, double lr, double beta1, double beta2, double eps, void* stream);
+
+/* Attach a network to a handle (NULL detaches): later preconditioner applications and
+   solves evaluate it on every subdomain right-hand side and offer the result as the
+   initial guess.  The network is borrowed (the caller keeps it alive while attached)
+   and must have tile >= every subdomain's nx, ny and max_batch >= nsub * nrhs.
+   Attaching allocates nothing. */
+dd_status dd_set_guess(dd_handle* h, dd_net* net);
+/* Network input tiles of all subdomain solves of global r (device complex128
+   [nrhs][ndof]): x device fp32 [nsub * nrhs][T][T][4] and the scales s (device double
+   [nsub * nrhs]). */
+dd_status dd_tiles(dd_handle* h, const void* r, int tile, float* x, double* scale, void* stream);
+/* t = s u as tiles from packed complex128 u [nrhs][nfine] (targets for training). */
+dd_status dd_packed_to_tiles(dd_handle* h, const void* u, const double* scale, int tile, float* t, void* stream);
+/* Host copy of the per-subdomain tile descriptions (nsub entries). */
+dd_status dd_tile_descs(const dd_handle* h, dd_tile_desc* out);
+/* Host copies of the per-solve inner iteration counts and flags (bit 0 guess accepted,
+   bit 1 not converged) of the last batched subdomain-solve launch of this handle
+   (nsub * nrhs entries each, solve rhs * nsub + sub; either pointer may be NULL).
+   Synchronises `stream`. */
+dd_status dd_last_inner(const dd_handle* h, int32_t* iters, int32_t* flags, void* stream);
+/* Copy the j-th outer FGMRES basis vector of the last solve (0 <= j <= its Krylov
+   dimension) to v (device complex128 [nrhs][ndof]). */
+dd_status dd_outer_basis(dd_handle* h, int j, void* v, void* stream);
 
 #ifdef __cplusplus
 }

@@ -22,8 +22,11 @@ pool: 2x2 average; up: 2x nearest; cat: channel concatenation (first operand fir
 Weights of a 3x3 layer are indexed [ky][kx][cin][cout] and act as
 out[y, x, co] = b[co] + sum_{ky, kx, ci} W[ky, kx, ci, co] in[y + ky - 1, x + kx - 1, ci].
 
-Loss (per batch): mean over samples of sum_p m_p |y_p - t_p|^2 / sum_p m_p |t_p|^2, with
-m the tile mask (1 on the subdomain's nodes) and t the target solution (normalised).
+Loss (per batch, see `loss`): a residual term ||B (y - t)||^2 / ||B t||^2 with B the
+subdomain operator, and an error term ||y - t||^2 / ||t||^2, both over the subdomain's
+nodes, with t the normalised target solution.  A guess u_j = y_j / s_j is kept by the
+subdomain solver only if it lowers the deflated residual (Sec. 2, eq. 4), which is why
+the residual term is the one the training weights most.
 """
 
 from __future__ import annotations
@@ -174,16 +177,104 @@ def backward(p, c, dy):
     return g
 
 
-def loss(y, t, m):
-    """Mean relative masked squared error and its gradient with respect to y."""
-    B = y.shape[0]
-    mm = m[..., None]
-    den = np.sum(mm * t * t, axis=(1, 2, 3))
-    den = np.where(den > 0, den, 1.0)
-    num = np.sum(mm * (y - t) ** 2, axis=(1, 2, 3))
-    L = float(np.mean(num / den))
-    dy = (2.0 / B) * mm * (y - t) / den[:, None, None, None]
-    return L, dy
+def loss(y, t, tiles, w_res=1.0, w_err=0.0):
+    """Training loss and its gradient with respect to y.
+
+    Sample b covers the nodes (x < nx_b, y < ny_b) of its tile; on them e = y - t is read
+    as the complex local vector (x fastest) and B_b is the subdomain operator:
+        L = mean_b ( w_res ||B_b e||^2 / ||B_b t||^2 + w_err ||e||^2 / ||t||^2 ),
+    d L / d(Re y, Im y) = (Re, Im) of (2 w_res B^H B e / ||B t||^2 + 2 w_err e / ||t||^2) / n_b.
+    `tiles` is a list of dicts with keys nx, ny and B (matrix, may be None when w_res = 0).
+    """
+    nb = y.shape[0]
+    dy = np.zeros_like(y)
+    total = 0.0
+    for b, tl in enumerate(tiles):
+        nx, ny = tl["nx"], tl["ny"]
+        ys = y[b, :ny, :nx, 0] + 1j * y[b, :ny, :nx, 1]
+        ts = t[b, :ny, :nx, 0] + 1j * t[b, :ny, :nx, 1]
+        e = (ys - ts).reshape(-1)
+        tv = ts.reshape(-1)
+        g = np.zeros_like(e)
+        if w_err:
+            den = np.vdot(tv, tv).real
+            den = den if den > 0 else 1.0
+            total += w_err * np.vdot(e, e).real / den
+            g += 2.0 * w_err * e / den
+        if w_res:
+            B = tl["B"]
+            r = B @ e
+            bt = B @ tv
+            den = np.vdot(bt, bt).real
+            den = den if den > 0 else 1.0
+            total += w_res * np.vdot(r, r).real / den
+            g += 2.0 * w_res * (B.conj().T @ r) / den
+        g = g.reshape(ny, nx) / nb
+        dy[b, :ny, :nx, 0] = g.real
+        dy[b, :ny, :nx, 1] = g.imag
+    return total / nb, dy
+
+
+# ---- tiles of a Schwarz problem (local right-hand sides and solutions) -------------------
+
+def impedance_node_mask(g, n: int) -> np.ndarray:
+    """[ny, nx] bool: local node lies on an impedance side of its subdomain (a side of the
+    overlapping rectangle that is interior to the domain and carries local nodes)."""
+    m = np.zeros((g.ny, g.nx), dtype=bool)
+    if g.i0 == g.ax and g.ax > 0:
+        m[:, 0] = True
+    if g.i1 == g.bx and g.bx < n:
+        m[:, -1] = True
+    if g.j0 == g.ay and g.ay > 0:
+        m[0, :] = True
+    if g.j1 == g.by and g.by < n:
+        m[-1, :] = True
+    return m
+
+
+def tile_inputs(S, r: np.ndarray, T: int, kh: float):
+    """Network inputs [nsub, T, T, 4] of the local right-hand sides R_j r and the scales
+    s_j = sqrt(n_j) / ||R_j r|| (0 for a zero right-hand side)."""
+    n = S.prob.n
+    x = np.zeros((len(S.subs), T, T, 4))
+    scale = np.zeros(len(S.subs))
+    for j, sd in enumerate(S.subs):
+        g = sd.geom
+        f = r[g.idx]
+        nrm = np.linalg.norm(f)
+        s = np.sqrt(g.ndof) / nrm if nrm > 0 else 0.0
+        scale[j] = s
+        fs = (s * f).reshape(g.ny, g.nx)
+        x[j, :g.ny, :g.nx, 0] = fs.real
+        x[j, :g.ny, :g.nx, 1] = fs.imag
+        x[j, :g.ny, :g.nx, 2] = kh
+        x[j, :g.ny, :g.nx, 3] = np.where(impedance_node_mask(g, n), -1.0, 1.0)
+    return x, scale
+
+
+def tile_targets(S, us, scale, T: int):
+    """Targets [nsub, T, T, 2] = s_j u_j placed like the inputs."""
+    t = np.zeros((len(S.subs), T, T, 2))
+    for j, sd in enumerate(S.subs):
+        g = sd.geom
+        u = (scale[j] * us[j]).reshape(g.ny, g.nx)
+        t[j, :g.ny, :g.nx, 0] = u.real
+        t[j, :g.ny, :g.nx, 1] = u.imag
+    return t
+
+
+def tile_operators(S):
+    return [{"nx": sd.geom.nx, "ny": sd.geom.ny, "B": sd.B} for sd in S.subs]
+
+
+def guesses(S, y, scale):
+    """Local initial guesses u_j = y_j / s_j from network outputs (zero where s_j = 0)."""
+    out = []
+    for j, sd in enumerate(S.subs):
+        g = sd.geom
+        v = y[j, :g.ny, :g.nx, 0] + 1j * y[j, :g.ny, :g.nx, 1]
+        out.append(v.reshape(-1) / scale[j] if scale[j] > 0 else np.zeros(g.ndof, dtype=complex))
+    return out
 
 
 def adam(p, g, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):

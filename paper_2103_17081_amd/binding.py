@@ -73,10 +73,31 @@ class Stats(ctypes.Structure):
         ("graph_replays", ctypes.c_int),
         ("timed_steps", ctypes.c_int),
         ("ms_steps", ctypes.c_double),
+        ("ms_guess", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NetParams(ctypes.Structure):
+    _fields_ = [
+        ("widths", ctypes.c_int * 4),
+        ("tile", ctypes.c_int),
+        ("max_batch", ctypes.c_int),
+        ("train", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong),
+    ]
+
+
+class TileDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int),
+        ("ny", ctypes.c_int),
+        ("edges", ctypes.c_int),
+        ("robin", ctypes.c_int),
+        ("kh", ctypes.c_double),
+    ]
 
 
 class DDError(RuntimeError):
@@ -114,6 +135,22 @@ _SIGS = {
     "dd_op_scatter": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "dd_op_inner_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), _VP]),
+    "dd_net_default_params": (None, [ctypes.POINTER(NetParams)]),
+    "dd_net_create": (ctypes.c_int, [ctypes.POINTER(NetParams), ctypes.POINTER(_VP)]),
+    "dd_net_destroy": (ctypes.c_int, [_VP]),
+    "dd_net_num_params": (ctypes.c_int64, [_VP]),
+    "dd_net_set_params": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+    "dd_net_get_params": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+    "dd_net_forward": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, _VP]),
+    "dd_net_gradient": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(TileDesc), ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    "dd_net_adam": (ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _VP]),
+    "dd_set_guess": (ctypes.c_int, [_VP, _VP]),
+    "dd_tiles": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, _VP, _VP]),
+    "dd_packed_to_tiles": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP, _VP]),
+    "dd_tile_descs": (ctypes.c_int, [_VP, ctypes.POINTER(TileDesc)]),
+    "dd_outer_basis": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP]),
+    "dd_last_inner": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _VP]),
 }
 
 
@@ -330,6 +367,130 @@ class Solver:
                                        flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        _stream(self.torch)), "dd_op_inner_solve")
         return u, iters, flags
+
+    # -- learned initial guess --
+    def set_guess(self, net):
+        """Attach a GuessNet (None detaches); the network must outlive the attachment."""
+        _check(lib().dd_set_guess(self._h, net._n if net is not None else None), "dd_set_guess")
+        self._net = net
+
+    def tiles(self, r, tile: int):
+        """Network input tiles of R_j r for every subdomain / rhs and their scales."""
+        B = self.nsub * self.nrhs
+        x = self.torch.empty((B, tile, tile, 4), dtype=self.torch.float32, device="cuda")
+        s = self.torch.empty(B, dtype=self.torch.float64, device="cuda")
+        _check(lib().dd_tiles(self._h, _ptr(r), tile, _ptr(x), _ptr(s), _stream(self.torch)), "dd_tiles")
+        return x, s
+
+    def packed_to_tiles(self, u, scale, tile: int):
+        B = self.nsub * self.nrhs
+        t = self.torch.empty((B, tile, tile, 2), dtype=self.torch.float32, device="cuda")
+        _check(lib().dd_packed_to_tiles(self._h, _ptr(u), _ptr(scale), tile, _ptr(t), _stream(self.torch)),
+               "dd_packed_to_tiles")
+        return t
+
+    def tile_descs(self):
+        arr = (TileDesc * self.nsub)()
+        _check(lib().dd_tile_descs(self._h, arr), "dd_tile_descs")
+        return arr
+
+    def last_inner(self):
+        """Per-solve inner iteration counts and flags of the last batched launch."""
+        cnt = self.nsub * self.nrhs
+        iters = np.zeros(cnt, dtype=np.int32)
+        flags = np.zeros(cnt, dtype=np.int32)
+        _check(lib().dd_last_inner(self._h, iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream(self.torch)),
+               "dd_last_inner")
+        return iters, flags
+
+    def outer_basis(self, j: int):
+        v = self.torch.empty((self.nrhs, self.ndof) if self.nrhs > 1 else (self.ndof,),
+                             dtype=self.torch.complex128, device="cuda")
+        _check(lib().dd_outer_basis(self._h, j, _ptr(v), _stream(self.torch)), "dd_outer_basis")
+        return v
+
+
+def default_net_params() -> NetParams:
+    p = NetParams()
+    lib().dd_net_default_params(ctypes.byref(p))
+    return p
+
+
+class GuessNet:
+    """Handle on one guess network (dd_net_create ... dd_net_destroy)."""
+
+    def __init__(self, widths=(16, 32, 64, 64), tile: int = 64, max_batch: int = 256, train: bool = False,
+                 seed: int | None = None):
+        p = default_net_params()
+        for i, w in enumerate(widths):
+            p.widths[i] = int(w)
+        p.tile, p.max_batch, p.train = tile, max_batch, 1 if train else 0
+        if seed is not None:
+            p.seed = seed
+        torch = _torch()
+        self.torch = torch
+        self._n = ctypes.c_void_p()
+        _check(lib().dd_net_create(ctypes.byref(p), ctypes.byref(self._n)), "dd_net_create")
+        self.widths, self.tile, self.max_batch = tuple(int(w) for w in widths), tile, max_batch
+        self.nparams = int(lib().dd_net_num_params(self._n))
+
+    def close(self):
+        if self._n:
+            lib().dd_net_destroy(self._n)
+            self._n = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.nparams, dtype=np.float32)
+        _check(lib().dd_net_get_params(self._n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), self.nparams),
+               "dd_net_get_params")
+        return out
+
+    def set_params(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        _check(lib().dd_net_set_params(self._n, v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), v.size),
+               "dd_net_set_params")
+
+    def forward(self, x):
+        """x: float32 GPU tensor [B, T, T, 4] -> y [B, T, T, 2]."""
+        y = self.torch.empty(x.shape[:3] + (2,), dtype=self.torch.float32, device="cuda")
+        _check(lib().dd_net_forward(self._n, _ptr(x), x.shape[0], _ptr(y), _stream(self.torch)), "dd_net_forward")
+        return y
+
+    def gradient(self, x, t, desc, w_res: float = 1.0, w_err: float = 0.0, want_grad: bool = False):
+        """Loss (and, if asked, the gradient as a GPU tensor) for a batch; desc: TileDesc array."""
+        g = self.torch.empty(self.nparams, dtype=self.torch.float32, device="cuda") if want_grad else None
+        loss = ctypes.c_double()
+        _check(lib().dd_net_gradient(self._n, _ptr(x), _ptr(t), desc, x.shape[0], w_res, w_err,
+                                     _ptr(g) if g is not None else None, ctypes.byref(loss), _stream(self.torch)),
+               "dd_net_gradient")
+        return loss.value, g
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _check(lib().dd_net_adam(self._n, lr, beta1, beta2, eps, _stream(self.torch)), "dd_net_adam")
+
+
+def net_create_status(**kw) -> tuple[int, str]:
+    """dd_net_create's status for parameters that fail validation (host-only, no device work)."""
+    p = default_net_params()
+    for key, val in kw.items():
+        if key == "widths":
+            for i, w in enumerate(val):
+                p.widths[i] = w
+        else:
+            setattr(p, key, val)
+    n = ctypes.c_void_p()
+    st = lib().dd_net_create(ctypes.byref(p), ctypes.byref(n))
+    msg = lib().dd_last_error().decode()
+    if st == DD_OK:
+        lib().dd_net_destroy(n)
+    return st, msg
 
 
 def setup_status(**kw) -> tuple[int, str]:

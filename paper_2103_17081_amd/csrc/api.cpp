@@ -13,6 +13,7 @@
 #include "ddhelm.h"
 #include "coarse.hpp"
 #include "kernels.hpp"
+#include "net_host.hpp"
 #include "outer.hpp"
 
 using ddh::cplx;
@@ -44,9 +45,13 @@ dd_status fail(dd_status s, const std::string& msg) {
 constexpr int kOuterBlocks = 1024;   // workgroups of the grid-stride outer kernels
 constexpr int kMaxRestart = 4000;    // Givens kernel stages a restart cycle in LDS
 constexpr int kMaxGraphSteps = 64;   // outer steps per captured graph
-constexpr int kEvPerStep = 6;        // phase events recorded per outer step
+constexpr int kEvPerStep = 7;        // phase events recorded per outer step
 
 }  // namespace
+
+namespace ddh {
+dd_status fail_msg(dd_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace ddh
 
 struct dd_handle {
   dd_params p{};
@@ -97,6 +102,7 @@ struct dd_handle {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  dd_net* net = nullptr;        // attached guess network (borrowed)
   std::vector<void*> allocs;
 
   template <typename T>
@@ -303,22 +309,47 @@ ddh::InnerArgs<T> inner_args(dd_handle* h) {
   return a;
 }
 
-// Preconditioner apply: z = M^{-1} r over all right-hand sides (those with done set are skipped).
-dd_status run_apply(dd_handle* h, const cplx<double>* r, long long rstride, cplx<double>* z, long long zstride,
+// Guess tiles of the attached network for the subdomain right-hand sides R_j r (no-op
+// without a network).
+dd_status run_guess(dd_handle* h, const cplx<double>* r, long long rstride, const int* done, hipStream_t st,
+                    const int* jdev = nullptr, long long rslot = 0) {
+  if (!h->net) return DD_OK;
+  ddh::TileArgs ta{};
+  ta.subs = h->subs;
+  ta.cs = h->cs;
+  ta.r = r;
+  ta.rstride = rstride;
+  ta.jdev = jdev;
+  ta.rslot = rslot;
+  ta.done = done;
+  return ddh::net_infer_from(h->net, ta, h->nsub, h->nrhs, st);
+}
+
+// Batched subdomain solves: z = M^{-1} r over all right-hand sides (those with done set
+// are skipped), starting from the network's guess tiles when a network is attached.
+dd_status run_inner(dd_handle* h, const cplx<double>* r, long long rstride, cplx<double>* z, long long zstride,
                     const int* done, hipStream_t st, const int* jdev = nullptr, long long rslot = 0,
                     long long zslot = 0) {
+  const float* gt = h->net ? h->net->y : nullptr;
+  const int gT = h->net ? h->net->T : 0;
   if (h->prec == 32) {
     auto a = inner_args<float>(h);
     a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
-    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot; a.gtile = gt; a.gT = gT;
     DD_HIP(ddh::launch_inner_solve<float>(a, st));
   } else {
     auto a = inner_args<double>(h);
     a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
-    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot; a.gtile = gt; a.gT = gT;
     DD_HIP(ddh::launch_inner_solve<double>(a, st));
   }
   return DD_OK;
+}
+
+dd_status run_apply(dd_handle* h, const cplx<double>* r, long long rstride, cplx<double>* z, long long zstride,
+                    const int* done, hipStream_t st) {
+  DD_TRY(run_guess(h, r, rstride, done, st));
+  return run_inner(h, r, rstride, z, zstride, done, st);
 }
 
 dd_status check_handle(const dd_handle* h) {
@@ -486,19 +517,21 @@ static dd_status enqueue_outer_step(dd_handle* h, int slot, hipStream_t st, bool
     return DD_OK;
   };
   DD_TRY(mark(0));
-  DD_TRY(run_apply(h, h->Vo, vstr, h->Zo, zstr, o.done, st, h->jdev, nd, nd));
+  DD_TRY(run_guess(h, h->Vo, vstr, o.done, st, h->jdev, nd));
   DD_TRY(mark(1));
-  DD_HIP(ddh::launch_global_apply_masked(h->cs, h->Zo, zstr, h->Vo + nd, vstr, nr, o.done, st, sr, nd, nd));
+  DD_TRY(run_inner(h, h->Vo, vstr, h->Zo, zstr, o.done, st, h->jdev, nd, nd));
   DD_TRY(mark(2));
+  DD_HIP(ddh::launch_global_apply_masked(h->cs, h->Zo, zstr, h->Vo + nd, vstr, nr, o.done, st, sr, nd, nd));
+  DD_TRY(mark(3));
   DD_HIP(ddh::launch_dots2(h->Vo, vstr, nullptr, 0, nullptr, 0, nd, sr, 1, m, h->part, h->pstride, nr, o.done, st,
                            h->dots_blocks));
-  DD_TRY(mark(3));
+  DD_TRY(mark(4));
   DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, sr, 2, 3, m, h->coef, h->pstride, nullptr, 0, 2, nr,
                                   o.done, st));
   DD_HIP(ddh::launch_dcgs2_step(o, sr, m, nd, h->coef, h->pstride, 1, h->ca, h->cb, m, h->scal, nr, st));
-  DD_TRY(mark(4));
-  DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, sr, h->ca, h->cb, m, h->scal, nr, o.done, st));
   DD_TRY(mark(5));
+  DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, sr, h->ca, h->cb, m, h->scal, nr, o.done, st));
+  DD_TRY(mark(6));
   DD_HIP(ddh::launch_advance_step(h->jdev, st));
   return DD_OK;
 }
@@ -539,7 +572,7 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
   DD_HIP(hipMemsetAsync(o.applies, 0, nr * sizeof(int), st));
   DD_HIP(hipMemsetAsync(o.sweep_bytes, 0, 2 * sizeof(unsigned long long), st));
   DD_HIP(hipMemsetAsync(u, 0, (size_t)nr * nd * sizeof(cplx<double>), st));
-  double ms[5] = {0, 0, 0, 0, 0};   // inner, global stencil, dot sweep, bookkeeping, update sweep
+  double ms[6] = {0, 0, 0, 0, 0, 0};   // guess, inner, global stencil, dot sweep, bookkeeping, update sweep
   double ms_steps = 0.0;            // all outer steps (graph replays and eager steps)
   int launches = 0, replays = 0, timed_steps = 0;
   float el = 0.f;
@@ -590,7 +623,7 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
         timed_steps += batch;
         for (int q = 0; q < batch; ++q) {
           hipEvent_t* ev = h->sev.data() + (size_t)q * kEvPerStep;
-          for (int e = 0; e < 5; ++e) {
+          for (int e = 0; e < 6; ++e) {
             DD_HIP(hipEventElapsedTime(&el, ev[e], ev[e + 1]));
             ms[e] += el;
           }
@@ -638,12 +671,13 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
     stats->inner_iters_max = (int)c[2];
     stats->guesses_accepted = (long long)c[3];
     stats->inner_bytes = (double)c[4];
-    stats->ms_inner = ms[0];
-    stats->ms_spmv = ms[1];
-    stats->ms_orth = ms[2] + ms[3] + ms[4];
-    stats->ms_other = ms[3];
-    stats->ms_dots = ms[2];
-    stats->ms_update = ms[4];
+    stats->ms_guess = ms[0];
+    stats->ms_inner = ms[1];
+    stats->ms_spmv = ms[2];
+    stats->ms_orth = ms[3] + ms[4] + ms[5];
+    stats->ms_other = ms[4];
+    stats->ms_dots = ms[3];
+    stats->ms_update = ms[5];
     stats->dots_bytes = (double)sb[0];
     stats->update_bytes = (double)sb[1];
     stats->inner_launches = launches;
@@ -908,6 +942,85 @@ dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void
   if (iters) DD_HIP(hipMemcpyAsync(iters, h->iters, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
   if (flags) DD_HIP(hipMemcpyAsync(flags, h->flags, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
   DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+// ---- learned initial guess ---------------------------------------------------------------
+
+dd_status dd_set_guess(dd_handle* h, dd_net* net) {
+  DD_TRY(check_handle(h));
+  if (net) {
+    for (const SubDesc& d : h->subs_h)
+      if (d.nx > net->T || d.ny > net->T)
+        return fail(DD_EINVAL, "network tile " + std::to_string(net->T) + " smaller than a subdomain tile (" +
+                                   std::to_string(d.nx) + " x " + std::to_string(d.ny) + ")");
+    if ((long long)h->nsub * h->nrhs > net->B)
+      return fail(DD_EINVAL, "network max_batch smaller than nsub * nrhs");
+  }
+  if (net != h->net) invalidate_graph(h);
+  h->net = net;
+  return DD_OK;
+}
+
+dd_status dd_tiles(dd_handle* h, const void* r, int tile, float* x, double* scale, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!r || !x || !scale) return fail(DD_EINVAL, "null argument");
+  for (const SubDesc& d : h->subs_h)
+    if (d.nx > tile || d.ny > tile) return fail(DD_EINVAL, "tile smaller than a subdomain tile");
+  ddh::TileArgs ta{};
+  ta.subs = h->subs;
+  ta.cs = h->cs;
+  ta.r = (const cplx<double>*)r;
+  ta.rstride = h->ndof;
+  ta.T = tile;
+  ta.xf = x;
+  ta.scale = scale;
+  DD_HIP(ddh::launch_tiles(ta, h->nsub, h->nrhs, (hipStream_t)stream));
+  return DD_OK;
+}
+
+dd_status dd_packed_to_tiles(dd_handle* h, const void* u, const double* scale, int tile, float* t, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!u || !scale || !t) return fail(DD_EINVAL, "null argument");
+  for (const SubDesc& d : h->subs_h)
+    if (d.nx > tile || d.ny > tile) return fail(DD_EINVAL, "tile smaller than a subdomain tile");
+  DD_HIP(ddh::launch_packed_to_tiles(h->subs, h->nsub, h->nrhs, h->nfine, (const cplx<double>*)u, scale, tile, t,
+                                     (hipStream_t)stream));
+  return DD_OK;
+}
+
+dd_status dd_tile_descs(const dd_handle* h, dd_tile_desc* out) {
+  DD_TRY(check_handle(h));
+  if (!out) return fail(DD_EINVAL, "null argument");
+  for (int j = 0; j < h->nsub; ++j) {
+    const SubDesc& d = h->subs_h[j];
+    out[j].nx = d.nx;
+    out[j].ny = d.ny;
+    out[j].edges = (d.i0 == d.ax ? 1 : 0) | (d.i0 + d.nx - 1 == d.bx ? 2 : 0) | (d.j0 == d.ay ? 4 : 0) |
+                   (d.j0 + d.ny - 1 == d.by ? 8 : 0);
+    out[j].robin = d.robin;
+    out[j].kh = h->cs.kh;
+  }
+  return DD_OK;
+}
+
+dd_status dd_last_inner(const dd_handle* h, int32_t* iters, int32_t* flags, void* stream) {
+  DD_TRY(check_handle(h));
+  hipStream_t st = (hipStream_t)stream;
+  const size_t cnt = (size_t)h->nsub * h->nrhs;
+  if (iters) DD_HIP(hipMemcpyAsync(iters, h->iters, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (flags) DD_HIP(hipMemcpyAsync(flags, h->flags, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+  DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+dd_status dd_outer_basis(dd_handle* h, int j, void* v, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!v) return fail(DD_EINVAL, "null argument");
+  if (j < 0 || j > h->restart) return fail(DD_EINVAL, "basis index out of range");
+  const long long nd = h->ndof, vstr = (long long)(h->restart + 1) * nd;
+  DD_HIP(hipMemcpy2DAsync(v, nd * sizeof(cplx<double>), h->Vo + (long long)j * nd, vstr * sizeof(cplx<double>),
+                          nd * sizeof(cplx<double>), h->nrhs, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return DD_OK;
 }
 

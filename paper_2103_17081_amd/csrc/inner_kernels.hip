@@ -309,15 +309,26 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   const double ref = tile_norm<T, NT>(d, L.B, L);
 
   bool accepted = false;
+  const bool offered = ref > 0.0 && (a.guess || a.gtile);
   int k = 0;
   bool converged = true;
   if (ref > 0.0) {
-    if (a.guess) {
-      const cplx<T>* gs = a.guess + fo;
-      const T gmul = T(fscale);
+    if (a.guess || a.gtile) {
+      // the solve runs on f / ||f||: a packed guess is scaled by 1 / ||f||, a network
+      // tile (scaled by sqrt(n_j) / ||f||) by 1 / sqrt(n_j)
+      const cplx<T>* gs = a.guess ? a.guess + fo : nullptr;
+      const float* gt = a.gtile ? a.gtile + (size_t)sidx * a.gT * a.gT * 2 : nullptr;
+      const T gmul = gt ? T(1.0 / sqrt((double)nj)) : T(fscale);
       for (int n = tid; n < nj; n += NT) {
         W[n] = L.B[n];
-        const cplx<T> gv = gmul * gs[n];
+        cplx<T> gv;
+        if (gt) {
+          const int lj = n / nx, li = n - lj * nx;
+          const float* q = gt + ((size_t)lj * a.gT + li) * 2;
+          gv = cplx<T>{gmul * T(q[0]), gmul * T(q[1])};
+        } else {
+          gv = gmul * gs[n];
+        }
         L.A[n] = gv;
         X[n] = gv;
       }
@@ -484,8 +495,9 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       const unsigned long long own = (unsigned long long)(d.oi1 - d.oi0 + 1) * (d.oj1 - d.oj0 + 1);
       const unsigned long long fac_bytes =
           16ull * ((unsigned long long)(2 * d.my - 1) * d.mx * d.mx + 3ull * d.mx * d.my);
-      const unsigned long long bytes = 16ull * nn + 16ull * own + (kk + 2) * fac_bytes +
-                                       s * nn * (2 * kk + 2 * kk * (kk + 1)) + 2 * s * nn;
+      unsigned long long bytes = 16ull * nn + 16ull * own + (kk + 2) * fac_bytes +
+                                 s * nn * (2 * kk + 2 * kk * (kk + 1)) + 2 * s * nn;
+      if (offered) bytes += fac_bytes + (a.gtile ? 8ull : s) * nn + 3 * s * nn;
       atomicAdd(a.counters + 4, bytes);
     }
   }

@@ -28,6 +28,10 @@ struct InnerArgs {
   cplx<T>* F;                    // packed local right-hand sides
   cplx<T>* U;                    // packed local solutions, or null
   const cplx<T>* guess;          // packed initial guesses, or null
+  const float* gtile;            // guess tiles [nrhs * nsub][gT][gT][2] of the guess network, or null;
+                                 // solve (rhs, sub) reads tile rhs * nsub + sub, values scaled by
+                                 // sqrt(n_j) / ||f_j||
+  int gT;
   cplx<T>* V;                    // Krylov bases: solve s at V + s_offset*(maxit+1)
   cplx<T>* W;                    // packed work vector
   cplx<T>* X;                    // packed work vector

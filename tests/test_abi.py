@@ -56,3 +56,34 @@ def test_null_arguments():
     assert L.dd_apply_preconditioner(None, None, None, None) == binding.DD_EINVAL
     assert L.dd_solve(None, None, None, None, None) == binding.DD_EINVAL
     assert L.dd_layout(None, None) == binding.DD_EINVAL
+
+
+def test_net_default_params():
+    p = binding.default_net_params()
+    assert list(p.widths) == [16, 32, 64, 64] and p.tile == 64 and p.max_batch == 256 and p.train == 0
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(tile=48), "tile must"),
+    (dict(widths=(16, 32, 48, 48)), "widths must"),
+    (dict(widths=(16, 32, 32, 64)), "c3 and c4"),
+    (dict(max_batch=0), "max_batch"),
+])
+def test_net_invalid_parameters_rejected_on_host(kw, needle):
+    st, msg = binding.net_create_status(**kw)
+    assert st == binding.DD_EINVAL
+    assert needle in msg
+
+
+def test_net_null_arguments():
+    L = binding.lib()
+    assert L.dd_net_create(None, None) == binding.DD_EINVAL
+    assert L.dd_net_destroy(None) == binding.DD_OK
+    assert L.dd_net_num_params(None) == 0
+    assert L.dd_net_forward(None, None, 1, None, None) == binding.DD_EINVAL
+    assert L.dd_net_gradient(None, None, None, None, 1, 1.0, 0.0, None, None, None) == binding.DD_EINVAL
+    assert L.dd_net_adam(None, 1e-3, 0.9, 0.999, 1e-8, None) == binding.DD_EINVAL
+    assert L.dd_set_guess(None, None) == binding.DD_EINVAL
+    assert L.dd_tile_descs(None, None) == binding.DD_EINVAL
+    assert L.dd_outer_basis(None, 0, None, None) == binding.DD_EINVAL
+    assert L.dd_last_inner(None, None, None, None) == binding.DD_EINVAL

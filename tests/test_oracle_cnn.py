@@ -2,8 +2,12 @@
 
 * a single-channel 3x3 convolution equals scipy.signal.correlate2d (zero fill);
 * pooling and upsampling backward passes are the adjoints of their forward passes;
-* every parameter gradient of the whole network, and the loss gradient, match central
+* every parameter gradient of the whole network, through both loss terms, matches central
   finite differences;
+* the loss vanishes at the target, is invariant under a common scaling of output and
+  target and ignores the padding outside the subdomain;
+* tiles of a Schwarz problem hold the scaled local right-hand sides, k h and the
+  impedance-side mask, and map the targets back to the local solutions;
 * one Adam step from zero state moves each parameter by lr * sign(gradient).
 """
 
@@ -38,15 +42,20 @@ def _net(seed=2, H=16):
         if k.startswith("b"):
             p[k] = 0.1 * rng.standard_normal(p[k].shape)
     x = rng.standard_normal((2, H, H, 4))
-    t = rng.standard_normal((2, H, H, 2))
-    m = (rng.uniform(size=(2, H, H)) > 0.3).astype(float)
-    return p, x, t, m, widths
+    t = np.zeros((2, H, H, 2))
+    tiles = []
+    for b, (nx, ny) in enumerate([(H - 3, H - 1), (H, H - 5)]):
+        t[b, :ny, :nx] = rng.standard_normal((ny, nx, 2))
+        n = nx * ny
+        B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        tiles.append({"nx": nx, "ny": ny, "B": B})
+    return p, x, t, tiles, widths
 
 
 def test_network_gradients_match_finite_differences():
-    p, x, t, m, widths = _net()
+    p, x, t, tiles, widths = _net()
     y, c = cnn.forward(p, x)
-    L, dy = cnn.loss(y, t, m)
+    L, dy = cnn.loss(y, t, tiles, w_res=1.0, w_err=0.5)
     g = cnn.backward(p, c, dy)
     rng = np.random.default_rng(3)
     eps = 1e-6
@@ -55,13 +64,52 @@ def test_network_gradients_match_finite_differences():
         for idx in rng.choice(flat.size, size=min(4, flat.size), replace=False):
             old = flat[idx]
             flat[idx] = old + eps
-            Lp, _ = cnn.loss(cnn.forward(p, x)[0], t, m)
+            Lp, _ = cnn.loss(cnn.forward(p, x)[0], t, tiles, 1.0, 0.5)
             flat[idx] = old - eps
-            Lm, _ = cnn.loss(cnn.forward(p, x)[0], t, m)
+            Lm, _ = cnn.loss(cnn.forward(p, x)[0], t, tiles, 1.0, 0.5)
             flat[idx] = old
             fd = (Lp - Lm) / (2 * eps)
             an = g[k].reshape(-1)[idx]
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (k, idx, fd, an)
+
+
+def test_loss_terms_vanish_at_target_and_scale_invariant():
+    _, _, t, tiles, _ = _net()
+    L, dy = cnn.loss(t.copy(), t, tiles, 1.0, 1.0)
+    assert L == 0.0 and not dy.any()
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal(t.shape)
+    L1, _ = cnn.loss(y, t, tiles, 1.0, 1.0)
+    L2, _ = cnn.loss(3.0 * y, 3.0 * t, tiles, 1.0, 1.0)
+    assert abs(L1 - L2) <= 1e-12 * L1
+    # outside the subdomain the output does not matter
+    y2 = y.copy()
+    y2[0, :, -3:] = 1e3
+    assert abs(cnn.loss(y2, t, tiles, 1.0, 1.0)[0] - L1) <= 1e-12 * L1
+
+
+def test_tiles_of_a_schwarz_problem():
+    """Inputs carry the scaled local right-hand side, k h and the boundary mask; the
+    guess built from the exact target reproduces the local solution."""
+    from oracle import schwarz
+    from paper_2103_17081_amd import inputs
+    w = inputs.workload("small")
+    S = schwarz.Schwarz(schwarz.problem_from_workload(w))
+    r = w.rhs[0]
+    kh = w.k / S.prob.n
+    x, s = cnn.tile_inputs(S, r, 32, kh)
+    for j, sd in enumerate(S.subs):
+        g = sd.geom
+        f = r[g.idx]
+        assert abs(np.sum(x[j, :, :, 0] ** 2 + x[j, :, :, 1] ** 2) - g.ndof) <= 1e-9 * g.ndof
+        assert np.all(x[j, :g.ny, :g.nx, 2] == kh) and not x[j, g.ny:, :, :].any()
+        # 2 x 2 partition: every subdomain has exactly two impedance sides
+        assert np.sum(x[j, :g.ny, :g.nx, 3] < 0) == g.nx + g.ny - 1
+        us = [sd.direct(r[sd.geom.idx]) for sd in S.subs]
+    t = cnn.tile_targets(S, us, s, 32)
+    gs = cnn.guesses(S, t, s)
+    for j, sd in enumerate(S.subs):
+        assert np.allclose(gs[j], us[j], rtol=0, atol=1e-12 * np.abs(us[j]).max())
 
 
 def test_flatten_roundtrip_and_order():
