@@ -123,6 +123,20 @@ class Workload:
         return (len(self.cuts_x) - 1) * (len(self.cuts_y) - 1)
 
 
+def training_problem(seed: int, block: int = 40) -> Workload:
+    """Seeded problem of the initial-guess training set: k ~ U[50, 250], ppwl drawn from
+    {10, 20}, N = n_intervals(k, ppwl), P x P blocks with P = max(2, round(N / block)) and
+    widths perturbed by +-25%, three seeded Gaussian sources; inner tol 1e-2."""
+    rng = np.random.default_rng(seed)
+    k = float(rng.uniform(50.0, 250.0))
+    ppwl = float(rng.choice([10.0, 20.0]))
+    n = n_intervals(k, ppwl)
+    parts = max(2, int(round(n / block)))
+    cx = perturbed_cuts(n, parts, 0.25, rng)
+    cy = perturbed_cuts(n, parts, 0.25, rng)
+    return Workload(f"train-{seed}", k, n, cx, cy, rhs=[gaussian_load(n, gaussian_params(rng))])
+
+
 def workload(name: str, nrhs: int = 1) -> Workload:
     """Preset problems.
 
