@@ -217,9 +217,34 @@ def ablation(w, net: GuessNet, precision: int = 32, vectors: int = 8):
     return out
 
 
+def applies(w, net: GuessNet, repeat: int = 20, precision: int = 32):
+    """`repeat` preconditioner applications of the normalised right-hand side with the
+    network attached, then `repeat` without (for kernel traces); returns the mean
+    inner iterations of the last application of each."""
+    import torch
+    f = torch.from_numpy(w.rhs[0]).to("cuda")
+    r = f / torch.linalg.vector_norm(f)
+    out = {}
+    with make_solver(w, precision) as s:
+        for mode in ("guess", "zero"):
+            s.set_guess(net if mode == "guess" else None)
+            for _ in range(repeat):
+                s.apply_preconditioner(r)
+            torch.cuda.synchronize()
+            it, fl = s.last_inner()
+            out[mode] = dict(mean_inner=float(it.mean()), accepted=float((fl & 1).mean()))
+        s.set_guess(None)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
+    for name in ("ablation", "applies"):
+        sp = sub.add_parser(name)
+        sp.add_argument("--weights", required=True)
+        sp.add_argument("--workload", default="large")
+        sp.add_argument("--repeat", type=int, default=20)
     tr = sub.add_parser("train")
     tr.add_argument("--out", required=True)
     tr.add_argument("--tile", type=int, default=64)
@@ -233,6 +258,14 @@ def main(argv=None):
     tr.add_argument("--eval", default="large", help="workload of the ablation after training ('' for none)")
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
+    if a.cmd in ("ablation", "applies"):
+        w = inputs.workload(a.workload)
+        head, _ = read_weights(a.weights)
+        net = load_net(a.weights, max_batch=len(w.cuts_x) ** 2, tile=head["tile"])
+        res = ablation(w, net) if a.cmd == "ablation" else applies(w, net, a.repeat)
+        log(json.dumps(res))
+        net.close()
+        return 0
     X, T, D, infos = build_dataset(range(1000, 1000 + a.problems), a.tile, a.vectors, log)
     Xv, Tv, Dv, _ = build_dataset([2000], a.tile, a.vectors, log)
     net = GuessNet(tile=a.tile, max_batch=max(a.batch, 256), train=True)
