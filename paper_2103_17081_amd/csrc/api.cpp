@@ -526,8 +526,8 @@ static dd_status enqueue_outer_step(dd_handle* h, int slot, hipStream_t st, bool
   DD_HIP(ddh::launch_dots2(h->Vo, vstr, nullptr, 0, nullptr, 0, nd, sr, 1, m, h->part, h->pstride, nr, o.done, st,
                            h->dots_blocks));
   DD_TRY(mark(4));
-  DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, sr, 2, 3, m, h->coef, h->pstride, nullptr, 0, 2, nr,
-                                  o.done, st));
+  DD_HIP(ddh::launch_reduce_parts(h->part, ddh::dots2_chunks(nd), h->pstride, sr, 2, 3, m, h->coef, h->pstride,
+                                  nullptr, 0, 2, nr, o.done, st));
   DD_HIP(ddh::launch_dcgs2_step(o, sr, m, nd, h->coef, h->pstride, 1, h->ca, h->cb, m, h->scal, nr, st));
   DD_TRY(mark(5));
   DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, sr, h->ca, h->cb, m, h->scal, nr, o.done, st));
@@ -593,8 +593,8 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
   while (true) {
     // beta = ||r||, g = (beta, 0, ..), v~_0 = r / beta, j = 0
     DD_HIP(ddh::launch_dots(h->Vo, vstr, h->Vo, vstr, nd, 0, 1, h->part, h->pstride, nr, nullptr, st));
-    DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, ddh::host_step(0), 0, 1, 0, h->coef, h->pstride,
-                                    nullptr, 0, 2, nr, nullptr, st));
+    DD_HIP(ddh::launch_reduce_parts(h->part, ddh::outer_chunks(nd), h->pstride, ddh::host_step(0), 0, 1, 0, h->coef,
+                                    h->pstride, nullptr, 0, 2, nr, nullptr, st));
     DD_HIP(ddh::launch_cycle_init(o, nr, st));
     DD_HIP(ddh::launch_scale(h->Vo, vstr, h->Vo, vstr, nd, o.hnext, kOuterBlocks, nr, o.done, st));
     DD_HIP(hipMemsetAsync(h->jdev, 0, sizeof(int), st));
@@ -635,8 +635,8 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
       // end of a cycle: finalise column m-1 from v~_m alone
       DD_HIP(ddh::launch_dots2(h->Vo, vstr, h->Vo + (long long)m * nd, vstr, nullptr, 0, nd, ddh::host_step(m), 0, m,
                                h->part, h->pstride, nr, o.done, st, h->dots_blocks));
-      DD_HIP(ddh::launch_reduce_parts(h->part, nd, h->pstride, ddh::host_step(m), 2, 3, m, h->coef, h->pstride,
-                                      nullptr, 0, 2, nr, o.done, st));
+      DD_HIP(ddh::launch_reduce_parts(h->part, ddh::dots2_chunks(nd), h->pstride, ddh::host_step(m), 2, 3, m,
+                                      h->coef, h->pstride, nullptr, 0, 2, nr, o.done, st));
       DD_HIP(ddh::launch_dcgs2_step(o, ddh::host_step(m), m, nd, h->coef, h->pstride, 0, h->ca, h->cb, m, h->scal,
                                     nr, st));
       DD_TRY(sync_done());

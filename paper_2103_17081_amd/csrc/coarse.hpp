@@ -191,9 +191,16 @@ __device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double
   const cplx<double>* __restrict__ F = fac + d.goff;
   const int L = coarse_group_lanes<NT>(d.mx);
   const int Q = (d.mx + L - 1) / L;
-  if (L == 16 && Q <= 2) detail::coarse_solve_ring<16, 2>(d, F, lc, t, a);
-  else if (L == 8 && Q <= 4) detail::coarse_solve_ring<8, 4>(d, F, lc, t, a);
-  else detail::coarse_solve_plain<NT>(d, F, lc, t, a);
+  // one ring shape per workgroup size (each instantiation costs registers in every
+  // kernel that contains it): 512 threads cover mx <= 32 with 16 lanes per row, 256
+  // threads with 8
+  if constexpr (NT >= 512) {
+    if (L == 16 && Q <= 2) detail::coarse_solve_ring<16, 2>(d, F, lc, t, a);
+    else detail::coarse_solve_plain<NT>(d, F, lc, t, a);
+  } else {
+    if (L == 8 && Q <= 4) detail::coarse_solve_ring<8, 4>(d, F, lc, t, a);
+    else detail::coarse_solve_plain<NT>(d, F, lc, t, a);
+  }
 }
 
 }  // namespace ddh

@@ -46,13 +46,15 @@ hipError_t launch_global_apply_masked(Consts cs, const cplx<double>* v, long lon
 hipError_t launch_advance_step(int* jdev, hipStream_t st);
 hipError_t launch_residual(const cplx<double>* f, long long fstride, cplx<double>* w, long long wstride,
                            long long ndof, int nblk, int nrhs, hipStream_t st);
-int outer_chunks(long long ndof);
+int outer_chunks(long long ndof);   // row chunks of the dots / update sweeps (part layout of launch_dots)
+__host__ __device__ int dots2_chunks(long long ndof);   // row chunks of launch_dots2 (its part layout)
 hipError_t configure_outer();
 hipError_t launch_fill_hash(cplx<double>* x, long long n, unsigned long long seed, hipStream_t st);   // dynamic-LDS limits of the bookkeeping kernels, at set-up
 hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<double>* w, long long wstride,
                        long long ndof, int nvec, int with_norm, cplx<double>* part, int pstride, int nrhs,
                        const int* done, hipStream_t st);
-hipError_t launch_reduce_parts(const cplx<double>* part, long long ndof, int pstride, StepRef sr, int mul, int add,
+// nchunk: the chunk count of the producing sweep (outer_chunks or dots2_chunks)
+hipError_t launch_reduce_parts(const cplx<double>* part, int nchunk, int pstride, StepRef sr, int mul, int add,
                                int jmax, cplx<double>* out, int ostride, cplx<double>* H, int hstride, int mode,
                                int nrhs, const int* done, hipStream_t st);
 hipError_t launch_update(const cplx<double>* basis, long long bstride, cplx<double>* w, long long wstride,

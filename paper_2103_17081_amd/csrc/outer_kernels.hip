@@ -139,12 +139,22 @@ __global__ void __launch_bounds__(256) dots_kernel(const cplx<double>* __restric
 // Delayed CGS2 pass 1: one sweep over the basis for two vectors.  Slots:
 // [0, nvec): conj(V_i) . x1;  [nvec, 2 nvec): conj(V_i) . x2 (if x2);
 // 2 nvec: |x1|^2;  2 nvec + 1: conj(x1) . x2;  2 nvec + 2: |x2|^2.
-// Work items are (row chunk of kChunkRows rows, group of kVecsPerBlock basis vectors);
-// the last group also produces the three self slots.  Blocks stride over the items,
-// so the grid is fixed while nvec grows; all loads of an item are issued before the
-// products are formed.  With `sr.jdev` set, nvec = *jdev and x1, x2 are basis
-// vectors nvec and nvec+1 (graph-captured steps); otherwise nvec = sr.jhost and
-// x1, x2 are the given vectors.
+// Work items are (row chunk of kD2Chunk rows, group of kD2Vecs basis vectors); the
+// last group also produces the three self slots.  Blocks take contiguous, chunk-major
+// item ranges, so x1, x2 are loaded once per chunk change; the grid is fixed while
+// nvec grows.  All loads of an item are issued before the products are formed, and
+// each thread covers kD2Rows rows so the per-item reduction (DPP sums over 16-lane
+// rows, then one LDS pass over the 16 row partials of the workgroup) is amortised over
+// 128 KB of basis.  With `sr.jdev` set, nvec = *jdev and x1, x2 are basis vectors nvec
+// and nvec+1 (graph-captured steps); otherwise nvec = sr.jhost and x1, x2 are the given
+// vectors.  part layout: [rhs][slot][chunk], dots2_chunks(ndof) chunks.
+constexpr int kD2Rows = 8;
+constexpr int kD2Vecs = 4;
+constexpr int kD2Chunk = kD2Rows * 256;
+constexpr int kD2Vals = 2 * (2 * kD2Vecs + 3);   // doubles reduced per item
+
+__host__ __device__ int dots2_chunks(long long ndof) { return (int)((ndof + kD2Chunk - 1) / kD2Chunk); }
+
 __global__ void __launch_bounds__(256) dots2_kernel(const cplx<double>* __restrict__ basis, long long bstride,
                                                     const cplx<double>* __restrict__ x1, long long x1stride,
                                                     const cplx<double>* __restrict__ x2, long long x2stride,
@@ -153,85 +163,91 @@ __global__ void __launch_bounds__(256) dots2_kernel(const cplx<double>* __restri
                                                     const int* __restrict__ done) {
   const int rhs = blockIdx.z;
   if (done && done[rhs]) return;
-  __shared__ cplx<double> red[4][2 * kVecsPerBlock + 3];
+  __shared__ double red[16][kD2Vals];
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int rowgrp = wave * 4 + lane / 16, li = lane % 16;
   const int nvec = sr.get();
   const bool two = two_in != 0;
   const cplx<double>* X1 = sr.jdev ? basis + rhs * bstride + (long long)nvec * ndof : x1 + rhs * x1stride;
   const cplx<double>* X2 = sr.jdev ? basis + rhs * bstride + (long long)(nvec + 1) * ndof
                                    : (two ? x2 + rhs * x2stride : nullptr);
-  const int nchunk = (int)((ndof + kChunkRows - 1) / kChunkRows);
-  const int ngroups = nvec > 0 ? (nvec + kVecsPerBlock - 1) / kVecsPerBlock : 1;
+  const cplx<double>* Vb = basis + rhs * bstride;
+  const int nchunk = dots2_chunks(ndof);
+  const int ngroups = nvec > 0 ? (nvec + kD2Vecs - 1) / kD2Vecs : 1;
   const long long items = (long long)nchunk * ngroups;
-  // contiguous, chunk-major item range: consecutive items share a row chunk, so x1, x2
-  // are loaded once per chunk change rather than once per item
   const long long lo = items * blockIdx.x / gridDim.x, hi = items * (blockIdx.x + 1) / gridDim.x;
   int cur = -1;
-  cplx<double> a[kRowsPerThread], b[kRowsPerThread];
+  cplx<double> a[kD2Rows], b[kD2Rows];
   for (long long item = lo; item < hi; ++item) {
     const int chunk = (int)(item / ngroups), group = (int)(item % ngroups);
-    const long long n0 = (long long)chunk * kChunkRows + tid;
+    const long long n0 = (long long)chunk * kD2Chunk + tid;
     if (chunk != cur) {
       cur = chunk;
 #pragma unroll
-      for (int r = 0; r < kRowsPerThread; ++r) {
+      for (int r = 0; r < kD2Rows; ++r) {
         const long long n = n0 + r * 256;
         a[r] = n < ndof ? X1[n] : czero<double>();
         b[r] = (two && n < ndof) ? X2[n] : czero<double>();
       }
     }
-    const int s0 = group * kVecsPerBlock;
-    const int s1 = min(nvec, s0 + kVecsPerBlock);
+    const int s0 = group * kD2Vecs;
+    const int s1 = min(nvec, s0 + kD2Vecs);
     const int cnt = s1 > s0 ? s1 - s0 : 0;
-    cplx<double> v[kVecsPerBlock][kRowsPerThread];
+    cplx<double> v[kD2Vecs][kD2Rows];
 #pragma unroll
-    for (int q = 0; q < kVecsPerBlock; ++q) {
+    for (int q = 0; q < kD2Vecs; ++q) {
 #pragma unroll
-      for (int r = 0; r < kRowsPerThread; ++r) {
+      for (int r = 0; r < kD2Rows; ++r) {
         const long long n = n0 + r * 256;
-        v[q][r] = (q < cnt && n < ndof) ? basis[rhs * bstride + (long long)(s0 + q) * ndof + n] : czero<double>();
+        v[q][r] = (q < cnt && n < ndof) ? Vb[(long long)(s0 + q) * ndof + n] : czero<double>();
       }
     }
+    double pv[kD2Vals];
 #pragma unroll
-    for (int q = 0; q < kVecsPerBlock; ++q) {
-      if (q < cnt) {
-        cplx<double> p1 = czero<double>(), p2 = czero<double>();
+    for (int q = 0; q < kD2Vecs; ++q) {
+      cplx<double> p1 = czero<double>(), p2 = czero<double>();
 #pragma unroll
-        for (int r = 0; r < kRowsPerThread; ++r) {
-          p1 = p1 + cmulc(v[q][r], a[r]);
-          if (two) p2 = p2 + cmulc(v[q][r], b[r]);
-        }
-        p1.re = wave_sum(p1.re); p1.im = wave_sum(p1.im);
-        if (lane == 0) red[wave][q] = p1;
-        if (two) {
-          p2.re = wave_sum(p2.re); p2.im = wave_sum(p2.im);
-          if (lane == 0) red[wave][kVecsPerBlock + q] = p2;
-        }
+      for (int r = 0; r < kD2Rows; ++r) {
+        p1 = p1 + cmulc(v[q][r], a[r]);
+        p2 = p2 + cmulc(v[q][r], b[r]);
       }
+      pv[2 * q] = p1.re;
+      pv[2 * q + 1] = p1.im;
+      pv[2 * (kD2Vecs + q)] = p2.re;
+      pv[2 * (kD2Vecs + q) + 1] = p2.im;
     }
     const bool self = group == ngroups - 1;
-    if (self) {
-      cplx<double> p[3] = {czero<double>(), czero<double>(), czero<double>()};
+    {
+      double s00 = 0.0, s22 = 0.0;
+      cplx<double> s01 = czero<double>();
 #pragma unroll
-      for (int r = 0; r < kRowsPerThread; ++r) {
-        p[0].re += cabs2(a[r]);
-        p[1] = p[1] + cmulc(a[r], b[r]);
-        p[2].re += cabs2(b[r]);
+      for (int r = 0; r < kD2Rows; ++r) {
+        s00 += cabs2(a[r]);
+        s01 = s01 + cmulc(a[r], b[r]);
+        s22 += cabs2(b[r]);
       }
+      pv[4 * kD2Vecs] = s00;
+      pv[4 * kD2Vecs + 1] = 0.0;
+      pv[4 * kD2Vecs + 2] = s01.re;
+      pv[4 * kD2Vecs + 3] = s01.im;
+      pv[4 * kD2Vecs + 4] = s22;
+      pv[4 * kD2Vecs + 5] = 0.0;
+    }
 #pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        p[e].re = wave_sum(p[e].re); p[e].im = wave_sum(p[e].im);
-        if (lane == 0) red[wave][2 * kVecsPerBlock + e] = p[e];
-      }
+    for (int e = 0; e < kD2Vals; ++e) {
+      const double t = row_sum<16>(pv[e]);
+      if (li == 0) red[rowgrp][e] = t;
     }
     __syncthreads();
-    if (tid < 2 * kVecsPerBlock + 3) {
+    if (tid < 2 * kD2Vecs + 3) {
       int slot = -1;
-      if (tid < kVecsPerBlock) slot = tid < cnt ? s0 + tid : -1;
-      else if (tid < 2 * kVecsPerBlock) slot = (two && tid - kVecsPerBlock < cnt) ? nvec + s0 + tid - kVecsPerBlock : -1;
-      else slot = self ? 2 * nvec + (tid - 2 * kVecsPerBlock) : -1;
+      if (tid < kD2Vecs) slot = tid < cnt ? s0 + tid : -1;
+      else if (tid < 2 * kD2Vecs) slot = (two && tid - kD2Vecs < cnt) ? nvec + s0 + tid - kD2Vecs : -1;
+      else slot = self ? 2 * nvec + (tid - 2 * kD2Vecs) : -1;
       if (slot >= 0) {
-        const cplx<double> t = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+        cplx<double> t = czero<double>();
+#pragma unroll
+        for (int g = 0; g < 16; ++g) t = t + cplx<double>{red[g][2 * tid], red[g][2 * tid + 1]};
         part[((long long)rhs * pstride + slot) * nchunk + chunk] = t;
       }
     }
@@ -679,11 +695,11 @@ hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_parts(const cplx<double>* part, long long ndof, int pstride, StepRef sr, int mul, int add,
+hipError_t launch_reduce_parts(const cplx<double>* part, int nchunk, int pstride, StepRef sr, int mul, int add,
                                int jmax, cplx<double>* out, int ostride, cplx<double>* H, int hstride, int mode,
                                int nrhs, const int* done, hipStream_t st) {
   const int grid = std::min(mul * jmax + add, 1024);
-  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid, nrhs), dim3(64), 0, st, part, outer_chunks(ndof), pstride, sr,
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid, nrhs), dim3(64), 0, st, part, nchunk, pstride, sr,
                      mul, add, out, ostride, H, hstride, mode, done);
   return hipGetLastError();
 }
@@ -707,8 +723,8 @@ hipError_t launch_scale(const cplx<double>* w, long long wstride, cplx<double>* 
 hipError_t launch_dots2(const cplx<double>* basis, long long bstride, const cplx<double>* x1, long long x1stride,
                         const cplx<double>* x2, long long x2stride, long long ndof, StepRef sr, int two, int jmax,
                         cplx<double>* part, int pstride, int nrhs, const int* done, hipStream_t st, int max_blocks) {
-  const int groups = jmax > 0 ? (jmax + kVecsPerBlock - 1) / kVecsPerBlock : 1;
-  const long long items = (long long)outer_chunks(ndof) * groups;
+  const int groups = jmax > 0 ? (jmax + kD2Vecs - 1) / kD2Vecs : 1;
+  const long long items = (long long)dots2_chunks(ndof) * groups;
   const int grid = (int)std::min<long long>(items, max_blocks > 0 ? max_blocks : kMaxSweepBlocks);
   // (each workgroup takes a contiguous range of about items / grid items)
   hipLaunchKernelGGL(dots2_kernel, dim3(grid, 1, nrhs), dim3(256), 0, st, basis, bstride, x1, x1stride, x2, x2stride,
