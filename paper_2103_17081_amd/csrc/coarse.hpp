@@ -56,8 +56,7 @@ namespace detail {
 // batch rather than once per step.
 template <int L, int Q>
 __device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<double>* __restrict__ F,
-                                                  const cplx<double>* lc, const cplx<double>* t,
-                                                  cplx<double>* a) {
+                                                  const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
   const int mx = d.mx, my = d.my, mm = mx * mx;
   const int r = threadIdx.x / L, l = threadIdx.x % L;
   const bool active = r < mx;
@@ -73,7 +72,9 @@ __device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<d
 #pragma unroll
   for (int q = 0; q < Q; ++q) eoff[q] = ok[q] ? r * mx + col[q] : 0;
   cplx<double> ring[kCoarseBatch][Q];
-  // forward: a_i = G_i (t_i - L_i a_{i-1}), G_i = block i
+  // forward: a_i = G_i (t_i - L_i a_{i-1}), G_i = block i.  The coupled right-hand side
+  // t_i - L_i a_{i-1} is formed once per column (threads 0..mx-1, in place in t) between
+  // the block products instead of by every row group.
   for (int i0 = 0; i0 < my; i0 += kCoarseBatch) {
 #pragma unroll
     for (int u = 0; u < kCoarseBatch; ++u) {
@@ -87,24 +88,24 @@ __device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<d
       if (i < my) {
         cplx<double> acc = czero<double>();
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int c = col[q];
-          if (ok[q]) {
-            cplx<double> rhs = t[i * mx + c];
-            if (i > 0) {
-              const cplx<double>* cpl = lc + 3 * (i * mx + c);
-              const cplx<double>* ap = a + (i - 1) * mx + c;
-              if (c > 0) rhs = rhs - cpl[0] * ap[-1];
-              rhs = rhs - cpl[1] * ap[0];
-              if (c < mx - 1) rhs = rhs - cpl[2] * ap[1];
-            }
-            acc = cfma(ring[u][q], rhs, acc);
-          }
-        }
+        for (int q = 0; q < Q; ++q)
+          if (ok[q]) acc = cfma(ring[u][q], t[i * mx + col[q]], acc);
         acc.re = row_sum<L>(acc.re);
         acc.im = row_sum<L>(acc.im);
         if (active && l == 0) a[i * mx + r] = acc;
         lds_barrier();
+        if (i + 1 < my) {
+          const int c = threadIdx.x;
+          if (c < mx) {
+            const cplx<double>* cpl = lc + 3 * ((i + 1) * mx + c);
+            const cplx<double>* ap = a + i * mx + c;
+            cplx<double> rhs = t[(i + 1) * mx + c] - cpl[1] * ap[0];
+            if (c > 0) rhs = rhs - cpl[0] * ap[-1];
+            if (c < mx - 1) rhs = rhs - cpl[2] * ap[1];
+            t[(i + 1) * mx + c] = rhs;
+          }
+          lds_barrier();
+        }
       }
     }
   }
@@ -136,8 +137,7 @@ __device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<d
 // General path for any mx <= kMaxMx: no prefetch, shuffle reductions.
 template <int NT>
 __device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<double>* __restrict__ F,
-                                                   const cplx<double>* lc, const cplx<double>* t,
-                                                   cplx<double>* a) {
+                                                   const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
   const int mx = d.mx, my = d.my, mm = mx * mx;
   const int L = coarse_group_lanes<NT>(mx);
   const int r = threadIdx.x / L, l = threadIdx.x % L;
@@ -180,14 +180,15 @@ __device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<
 }  // namespace detail
 
 // y = E^{-1} t for one subdomain, workgroup-cooperative (NT threads).  `t` and `a`
-// are n_c-entry LDS arrays (must not alias); the result overwrites `a`; `lc` holds
+// are n_c-entry LDS arrays (must not alias); the result overwrites `a` and `t` is
+// used as scratch (its content is lost); `lc` holds
 // the lower couplings staged by stage_lower.  `fac` is the handle's factor base (the
 // subdomain offset is applied here).  Block row r of each step is handled by a group
 // of lanes that split its columns and reduce with DPP row operations, so every step
 // costs one LDS-only barrier; factor entries are fetched a batch of steps at a time.
 template <int NT>
 __device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double>* __restrict__ fac,
-                                             const cplx<double>* lc, const cplx<double>* t, cplx<double>* a) {
+                                             const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
   const cplx<double>* __restrict__ F = fac + d.goff;
   const int L = coarse_group_lanes<NT>(d.mx);
   const int Q = (d.mx + L - 1) / L;
