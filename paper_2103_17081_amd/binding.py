@@ -166,6 +166,9 @@ def lib() -> ctypes.CDLL:
     """Load libddhelm.so (raises if it was not built)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime: load it first so that this library binds to the
+        # same runtime instance (two runtimes in one process cannot see each other's code)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_17081_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
