@@ -62,7 +62,8 @@ typedef struct {
   int overlap;         /* mesh-element layers appended on each interior side (>= 1; Sec. 3) */
   int local_bc;        /* DD_LOCAL_IMPEDANCE: B_j = K_j - k^2 M_j - i k M_Gamma_j (optimised
                           interface condition); DD_LOCAL_DIRICHLET: A_j = R_j A R_j^T (eq. 3) */
-  int deflation;       /* DD_DEFLATION_LINEAR (H = 2h interpolation); Bezier is rejected */
+  int deflation;       /* DD_DEFLATION_LINEAR (H = 2h interpolation) or DD_DEFLATION_BEZIER (the
+                          quadratic rational Bezier stencil 1/8 [1 4 6 4 1] of Sec. 2, read as Z^T) */
   int inner_precision; /* 64: complex128 subdomain Krylov work; 32: complex64.  The coarse
                           solve and the outer FGMRES are FP64 in both. */
   double inner_tol;    /* relative tolerance of each subdomain GMRES on ||P_j f_j|| (Sec. 3) */
@@ -163,8 +164,9 @@ int64_t dd_packed_coarse_size(const dd_handle* h);
    fine offset, coarse offset (offsets fit in int for every supported size). */
 dd_status dd_layout(const dd_handle* h, int32_t* out);
 
-/* Host copy of the nine coefficients of E_j per coarse node (complex128, [nc][9],
-   neighbour (cx+dx, cy+dy) at 3(dy+1) + (dx+1)) and min |pivot| of its block LU. */
+/* Host copy of the coefficients of E_j per coarse node (complex128, [nc][K]; K = 9 for
+   linear deflation, neighbour (cx+dx, cy+dy) at 3(dy+1) + (dx+1); K = 25 for Bezier,
+   neighbour at 5(dy+2) + (dx+2)) and min |pivot| of its block LU. */
 dd_status dd_coarse_matrix(const dd_handle* h, int j, double* out, double* min_pivot);
 
 /* ---- kernel-level entry points (parity tests, profiling) ------------------------ */

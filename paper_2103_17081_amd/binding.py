@@ -281,13 +281,15 @@ class Solver:
                                 device="cuda")
 
     def coarse_matrix(self, j: int):
-        """Host copy of E_j's nine coefficients per coarse node ([nc, 9] complex) and min |pivot|."""
+        """Host copy of E_j's coefficients per coarse node ([nc, 9] complex for linear deflation,
+        [nc, 25] for Bezier) and min |pivot|."""
         mx, my = int(self.layout[j, 8]), int(self.layout[j, 9])
-        out = np.zeros(mx * my * 9 * 2)
+        K = 9 if self.params.deflation == 0 else 25
+        out = np.zeros(mx * my * K * 2)
         piv = ctypes.c_double()
         _check(lib().dd_coarse_matrix(self._h, j, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       ctypes.byref(piv)), "dd_coarse_matrix")
-        return out.view(np.complex128).reshape(mx * my, 9), piv.value
+        return out.view(np.complex128).reshape(mx * my, K), piv.value
 
     def autotune(self, cache_path=None) -> str:
         buf = ctypes.create_string_buffer(4096)

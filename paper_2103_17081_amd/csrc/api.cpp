@@ -15,6 +15,7 @@
 #include "kernels.hpp"
 #include "net_host.hpp"
 #include "outer.hpp"
+#include "stencil.hpp"
 
 using ddh::cplx;
 using ddh::SubDesc;
@@ -175,8 +176,8 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   if (p->overlap < 1) return fail(DD_EINVAL, "overlap must be at least one element layer");
   if (p->local_bc != DD_LOCAL_IMPEDANCE && p->local_bc != DD_LOCAL_DIRICHLET)
     return fail(DD_EINVAL, "local_bc must be DD_LOCAL_IMPEDANCE or DD_LOCAL_DIRICHLET");
-  if (p->deflation != DD_DEFLATION_LINEAR)
-    return fail(DD_EINVAL, "only linear deflation (H = 2h) is implemented on the GPU");
+  if (p->deflation != DD_DEFLATION_LINEAR && p->deflation != DD_DEFLATION_BEZIER)
+    return fail(DD_EINVAL, "deflation must be DD_DEFLATION_LINEAR or DD_DEFLATION_BEZIER");
   if (p->inner_precision != 64 && p->inner_precision != 32) return fail(DD_EINVAL, "inner_precision must be 64 or 32");
   if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return fail(DD_EINVAL, "inner_tol must be in (0, 1)");
   if (p->inner_maxit < 1 || p->inner_maxit > 1000) return fail(DD_EINVAL, "inner_maxit must be in [1, 1000]");
@@ -230,15 +231,24 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
       d.oi0 = std::max(h->cuts_x[qx], 1); d.oi1 = h->cuts_x[qx + 1] - 1;
       d.oj0 = std::max(h->cuts_y[qy], 1); d.oj1 = h->cuts_y[qy + 1] - 1;
       d.mx = d.nx / 2; d.my = d.ny / 2;
-      if (d.mx > ddh::kMaxMx) return fail(DD_EINVAL, "subdomain too wide for the coarse kernels (mx > 128)");
+      d.defl = p->deflation;
+      if (d.defl == DD_DEFLATION_LINEAR) {
+        d.bmx = d.mx; d.bmy = d.my;
+      } else {
+        d.bmx = 2 * d.mx; d.bmy = (d.my + 1) / 2;
+      }
+      d.ncp = d.bmx * d.bmy;
+      if (d.bmx > ddh::kMaxMx)
+        return fail(DD_EINVAL, "subdomain too wide for the coarse kernels (coarse block size > 128)");
       d.robin = 0;
       if (imp) d.robin = (d.ax > 0 ? 1 : 0) | (d.bx < n ? 2 : 0) | (d.ay > 0 ? 4 : 0) | (d.by < n ? 8 : 0);
       d.off = off; d.coff = coff; d.goff = goff;
       off += (long long)d.nx * d.ny;
       coff += (long long)d.mx * d.my;
-      goff += ddh::coarse_factor_size(d.mx, d.my);
+      goff += d.defl == DD_DEFLATION_LINEAR ? ddh::coarse_factor_size(d.mx, d.my)
+                                            : ddh::coarse_factor_size_paired(d.bmx, d.bmy);
       h->max_nj = std::max(h->max_nj, d.nx * d.ny);
-      h->max_nc = std::max(h->max_nc, d.mx * d.my);
+      h->max_nc = std::max(h->max_nc, d.ncp);
       h->subs_h.push_back(d);
     }
   }
@@ -385,11 +395,14 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     });
     DD_TRY(h->alloc(&h->order, ord.size()));
     DD_HIP(hipMemcpy(h->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice));
-    DD_TRY(h->alloc(&h->Ec, (size_t)h->ncoarse * 9));
+    DD_TRY(h->alloc(&h->Ec, (size_t)h->ncoarse * ddh::coarse_coefs(h->p.deflation)));
     DD_TRY(h->alloc(&h->fac, (size_t)h->nfac));
     DD_TRY(h->alloc(&h->pivmin, h->nsub));
     DD_HIP(ddh::launch_assemble_coarse(h->subs, h->nsub, h->cs, h->p.local_bc, h->Ec, st));
-    DD_HIP(ddh::launch_factor_coarse(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
+    if (h->p.deflation == DD_DEFLATION_LINEAR)
+      DD_HIP(ddh::launch_factor_coarse(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
+    else
+      DD_HIP(ddh::launch_factor_coarse_paired(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
     h->pivmin_h.resize(h->nsub);
     DD_HIP(hipMemcpyAsync(h->pivmin_h.data(), h->pivmin, h->nsub * sizeof(double), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
@@ -491,7 +504,8 @@ dd_status dd_coarse_matrix(const dd_handle* h, int j, double* out, double* min_p
   DD_TRY(check_handle(h));
   if (j < 0 || j >= h->nsub || !out) return fail(DD_EINVAL, "bad subdomain index or null output");
   const SubDesc& d = h->subs_h[j];
-  DD_HIP(hipMemcpy(out, h->Ec + d.coff * 9, (size_t)d.mx * d.my * 9 * sizeof(cplx<double>), hipMemcpyDeviceToHost));
+  const int K = ddh::coarse_coefs(h->p.deflation);
+  DD_HIP(hipMemcpy(out, h->Ec + d.coff * K, (size_t)d.mx * d.my * K * sizeof(cplx<double>), hipMemcpyDeviceToHost));
   if (min_pivot) *min_pivot = h->pivmin_h[j];
   return DD_OK;
 }

@@ -29,6 +29,22 @@ __host__ __device__ __forceinline__ long long coarse_factor_size(int mx, int my)
   return (long long)(2 * my - 1) * mx * mx;
 }
 
+// Bezier deflation couples coarse nodes up to two rows apart, so its E is taken as
+// block tridiagonal over pairs of coarse rows (block size bmx = 2 mx, bmy block rows; an
+// odd last row is padded with an identity row).  Its factors: G_0..G_{bmy-1},
+// H_0..H_{bmy-2}, then the dense lower couplings L_1..L_{bmy-1}, each bmx x bmx
+// row-major.  The solve is a_I = G_I (t_I - L_I a_{I-1}), y_I = a_I - H_I y_{I+1}.
+__host__ __device__ __forceinline__ long long coarse_factor_size_paired(int bmx, int bmy) {
+  return (long long)(3 * bmy - 2) * bmx * bmx;
+}
+
+// Factor entries (complex<double>) one coarse solve of subdomain d reads, plus the
+// staged lower couplings of E for linear deflation.
+__host__ __device__ __forceinline__ long long coarse_solve_values(const SubDesc& d) {
+  return d.defl == 0 ? coarse_factor_size(d.mx, d.my) + 3LL * d.mx * d.my
+                     : coarse_factor_size_paired(d.bmx, d.bmy);
+}
+
 // Lanes per block row in the coarse solve: the largest power of two up to 16 with
 // lanes * mx <= NT.
 template <int NT>
@@ -43,6 +59,7 @@ __host__ __device__ __forceinline__ int coarse_group_lanes(int mx) {
 // caller synchronises before the first coarse_solve.
 __device__ __forceinline__ void stage_lower(const SubDesc& d, const cplx<double>* __restrict__ Ec,
                                             cplx<double>* lc) {
+  if (d.defl != 0) return;   // the paired (Bezier) solve keeps its couplings with the factors
   const int nc = d.mx * d.my;
   const cplx<double>* ec = Ec + d.coff * 9;
   for (int e = threadIdx.x; e < 3 * nc; e += blockDim.x) lc[e] = ec[(size_t)(e / 3) * 9 + e % 3];
@@ -177,19 +194,69 @@ __device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<
   }
 }
 
+// Paired-row (Bezier) block solve with dense lower couplings; shuffle reductions over
+// groups of L lanes, one LDS barrier per block product.
+template <int NT>
+__device__ __forceinline__ void coarse_solve_paired(const SubDesc& d, const cplx<double>* __restrict__ F,
+                                                    cplx<double>* t, cplx<double>* a) {
+  const int bm = d.bmx, bn = d.bmy, mm = bm * bm;
+  const int L = coarse_group_lanes<NT>(bm);
+  const int r = threadIdx.x / L, l = threadIdx.x % L;
+  const bool active = r < bm;
+  auto gsum = [&](cplx<double> v) {
+    for (int o = L >> 1; o > 0; o >>= 1) {
+      v.re += __shfl_xor(v.re, o, kWave);
+      v.im += __shfl_xor(v.im, o, kWave);
+    }
+    return v;
+  };
+  for (int I = 0; I < bn; ++I) {
+    if (I > 0) {
+      const cplx<double>* Lb = F + (size_t)(2 * bn - 2 + I) * mm;
+      cplx<double> acc = czero<double>();
+      if (active)
+        for (int c = l; c < bm; c += L) acc = cfma(Lb[r * bm + c], a[(I - 1) * bm + c], acc);
+      acc = gsum(acc);
+      if (active && l == 0) t[I * bm + r] = t[I * bm + r] - acc;
+      lds_barrier();
+    }
+    const cplx<double>* G = F + (size_t)I * mm;
+    cplx<double> acc = czero<double>();
+    if (active)
+      for (int c = l; c < bm; c += L) acc = cfma(G[r * bm + c], t[I * bm + c], acc);
+    acc = gsum(acc);
+    if (active && l == 0) a[I * bm + r] = acc;
+    lds_barrier();
+  }
+  for (int I = bn - 2; I >= 0; --I) {
+    const cplx<double>* H = F + (size_t)(bn + I) * mm;
+    cplx<double> acc = czero<double>();
+    if (active)
+      for (int c = l; c < bm; c += L) acc = cfma(H[r * bm + c], a[(I + 1) * bm + c], acc);
+    acc = gsum(acc);
+    if (active && l == 0) a[I * bm + r] = a[I * bm + r] - acc;
+    lds_barrier();
+  }
+}
+
 }  // namespace detail
 
 // y = E^{-1} t for one subdomain, workgroup-cooperative (NT threads).  `t` and `a`
-// are n_c-entry LDS arrays (must not alias); the result overwrites `a` and `t` is
-// used as scratch (its content is lost); `lc` holds
-// the lower couplings staged by stage_lower.  `fac` is the handle's factor base (the
-// subdomain offset is applied here).  Block row r of each step is handled by a group
-// of lanes that split its columns and reduce with DPP row operations, so every step
-// costs one LDS-only barrier; factor entries are fetched a batch of steps at a time.
+// are d.ncp-entry LDS arrays (must not alias; entries from mx * my on are zero
+// padding); the result overwrites `a` and `t` is used as scratch (its content is
+// lost); `lc` holds the lower couplings staged by stage_lower (linear deflation).
+// `fac` is the handle's factor base (the subdomain offset is applied here).  Block row
+// r of each step is handled by a group of lanes that split its columns and reduce with
+// DPP row operations, so every step costs one LDS-only barrier (two for the forward
+// steps); factor entries are fetched a batch of steps at a time.
 template <int NT>
 __device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double>* __restrict__ fac,
                                              const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
   const cplx<double>* __restrict__ F = fac + d.goff;
+  if (d.defl != 0) {
+    detail::coarse_solve_paired<NT>(d, F, t, a);
+    return;
+  }
   const int L = coarse_group_lanes<NT>(d.mx);
   const int Q = (d.mx + L - 1) / L;
   // one ring shape per workgroup size (each instantiation costs registers in every

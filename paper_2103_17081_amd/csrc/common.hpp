@@ -71,8 +71,12 @@ struct SubDesc {
   int i0, j0, nx, ny;
   int ax, bx, ay, by;
   int oi0, oi1, oj0, oj1;
-  int mx, my;        // coarse grid mx * my (linear deflation, H = 2h)
+  int mx, my;        // coarse grid mx * my (coarse node c on fine node 2c + 1 per direction)
   int robin;
+  int defl;          // deflation vectors: 0 linear interpolation, 1 quadratic Bezier
+  int bmx, bmy;      // block LU of E: bmy block rows of bmx unknowns (linear: mx, my;
+                     // Bezier: pairs of coarse rows, 2 mx and ceil(my / 2))
+  int ncp;           // coarse vector length of the solve, bmx * bmy (>= mx * my)
   int pad;
   long long off;     // offset of the tile in packed fine vectors (elements)
   long long coff;    // offset in packed coarse vectors (elements)

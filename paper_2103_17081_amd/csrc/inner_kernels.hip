@@ -107,10 +107,28 @@ __device__ __forceinline__ void apply_B(const SubDesc& d, const cplx<T>* tab, co
   }
 }
 
-// t = Z^T v (linear interpolation transpose), accumulated in double.
+// t = Z^T v, accumulated in double.  With `padded`, t is a coarse-solve LDS array and
+// its entries from mx * my up to the solve length ncp are set to 0.
 template <typename T>
-__device__ __forceinline__ void restrict_to(const SubDesc& d, const cplx<T>* v, cplx<double>* t) {
+__device__ __forceinline__ void restrict_to(const SubDesc& d, const cplx<T>* v, cplx<double>* t,
+                                            bool padded = true) {
   const int nc = d.mx * d.my;
+  if (d.defl != kLinear) {
+    const int nout = padded ? d.ncp : nc;
+    for (int c = threadIdx.x; c < nout; c += blockDim.x) {
+      cplx<double> acc = czero<double>();
+      if (c < nc) {
+        const int cy = c / d.mx, cx = c - cy * d.mx;
+        for (int py = max(2 * cy - 1, 0); py <= 2 * cy + 3 && py < d.ny; ++py) {
+          const double wy = zweight_kind(kBezier, py, cy);
+          for (int px = max(2 * cx - 1, 0); px <= 2 * cx + 3 && px < d.nx; ++px)
+            acc = acc + (wy * zweight_kind(kBezier, px, cx)) * ccast<double>(v[py * d.nx + px]);
+        }
+      }
+      t[c] = acc;
+    }
+    return;
+  }
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
     const int cy = c / d.mx, cx = c - cy * d.mx;
     cplx<double> acc = czero<double>();
@@ -126,6 +144,22 @@ __device__ __forceinline__ void restrict_to(const SubDesc& d, const cplx<T>* v, 
 
 // Z y at fine node (li, lj).
 __device__ __forceinline__ cplx<double> prolong_at(const SubDesc& d, const cplx<double>* y, int li, int lj) {
+  if (d.defl != kLinear) {
+    // coarse nodes within distance 2 of the fine node: c in [(i - 3) / 2, (i + 1) / 2]
+    const int ca = (li - 3) >> 1, cb = (lj - 3) >> 1;
+    cplx<double> acc = czero<double>();
+#pragma unroll
+    for (int b = cb; b <= cb + 2; ++b) {
+      if (b < 0 || b >= d.my) continue;
+      const double wy = zweight_kind(kBezier, lj, b);
+#pragma unroll
+      for (int a2 = ca; a2 <= ca + 2; ++a2) {
+        if (a2 < 0 || a2 >= d.mx) continue;
+        acc = acc + (wy * zweight_kind(kBezier, li, a2)) * y[b * d.mx + a2];
+      }
+    }
+    return acc;
+  }
   const int ca = (li - 1) >> 1, cb = (lj - 1) >> 1;
   cplx<double> acc = czero<double>();
 #pragma unroll
@@ -493,8 +527,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       if (accepted) atomicAdd(a.counters + 3, 1ull);
       const unsigned long long s = sizeof(cplx<T>), nn = (unsigned long long)nj, kk = (unsigned long long)k;
       const unsigned long long own = (unsigned long long)(d.oi1 - d.oi0 + 1) * (d.oj1 - d.oj0 + 1);
-      const unsigned long long fac_bytes =
-          16ull * ((unsigned long long)(2 * d.my - 1) * d.mx * d.mx + 3ull * d.mx * d.my);
+      const unsigned long long fac_bytes = 16ull * (unsigned long long)coarse_solve_values(d);
       unsigned long long bytes = 16ull * nn + 16ull * own + (kk + 2) * fac_bytes +
                                  s * nn * (2 * kk + 2 * kk * (kk + 1)) + 2 * s * nn;
       if (offered) bytes += fac_bytes + (a.gtile ? 8ull : s) * nn + 3 * s * nn;
@@ -578,7 +611,7 @@ __global__ void __launch_bounds__(kBlock) restrict_kernel(const SubDesc* __restr
                                                            const cplx<double>* __restrict__ v,
                                                            cplx<double>* __restrict__ t) {
   const SubDesc d = subs[blockIdx.x];
-  restrict_to(d, v + d.off, t + d.coff);
+  restrict_to(d, v + d.off, t + d.coff, false);
 }
 
 hipError_t launch_restrict(const SubDesc* subs, int nsub, const cplx<double>* v, cplx<double>* t,
@@ -611,7 +644,7 @@ __global__ void __launch_bounds__(kBlock) coarse_solve_kernel(const SubDesc* __r
   cplx<double>* ca = ct + max_nc;
   cplx<double>* lc = ca + max_nc;
   const int nc = d.mx * d.my;
-  for (int c = threadIdx.x; c < nc; c += blockDim.x) ct[c] = t[d.coff + c];
+  for (int c = threadIdx.x; c < d.ncp; c += blockDim.x) ct[c] = c < nc ? t[d.coff + c] : czero<double>();
   stage_lower(d, Ec, lc);
   __syncthreads();
   coarse_solve<kBlock>(d, fac, lc, ct, ca);

@@ -10,6 +10,8 @@ hipError_t launch_assemble_coarse(const SubDesc* subs, int nsub, Consts cs, int 
                                   hipStream_t st);
 hipError_t launch_factor_coarse(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
                                 double* pivmin, hipStream_t st);
+hipError_t launch_factor_coarse_paired(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
+                                       double* pivmin, hipStream_t st);
 
 // ---- subdomain solves ---------------------------------------------------------
 // Everything one batched launch of subdomain solves needs.  Packed fine vectors

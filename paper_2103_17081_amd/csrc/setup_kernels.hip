@@ -10,34 +10,37 @@ namespace ddh {
 __constant__ int kSx[kStencilPts] = {0, -1, 1, 0, 0, -1, 1};
 __constant__ int kSy[kStencilPts] = {0, 0, 0, -1, 1, -1, 1};
 
-// E(c, c+d) = sum_p Z(p, c) sum_q B(p, q) Z(q, c+d), p over the 3x3 support of Z_c.
+// E(c, c+d) = sum_p Z(p, c) sum_q B(p, q) Z(q, c+d), p over the support of Z_c
+// (3 x 3 fine nodes for linear deflation, 5 x 5 for Bezier); coarse_coefs(kind) values
+// per coarse node.
 __global__ void __launch_bounds__(kBlock) assemble_coarse_kernel(const SubDesc* __restrict__ subs, Consts cs,
                                                                   int local_bc, cplx<double>* __restrict__ Ec) {
   const SubDesc d = subs[blockIdx.x];
   __shared__ cplx<double> tab[kClasses * kStencilPts];
   build_class_table<double>(d.robin, cs.kh, cs.kh2, tab);
   __syncthreads();
+  const int kind = d.defl, R = zreach(kind), W = 2 * R + 1, K = W * W;
   const int nc = d.mx * d.my;
-  for (int e = threadIdx.x; e < nc * 9; e += blockDim.x) {
-    const int c = e / 9, o = e % 9;
+  for (int e = threadIdx.x; e < nc * K; e += blockDim.x) {
+    const int c = e / K, o = e % K;
     const int cx = c % d.mx, cy = c / d.mx;
-    const int qx = cx + o % 3 - 1, qy = cy + o / 3 - 1;
+    const int qx = cx + o % W - R, qy = cy + o / W - R;
     cplx<double> acc = czero<double>();
     if (qx >= 0 && qx < d.mx && qy >= 0 && qy < d.my) {
-      for (int py = 2 * cy; py <= 2 * cy + 2 && py < d.ny; ++py) {
-        for (int px = 2 * cx; px <= 2 * cx + 2 && px < d.nx; ++px) {
-          const double wz = zweight(px, cx) * zweight(py, cy);
+      for (int py = max(2 * cy + 1 - R, 0); py <= 2 * cy + 1 + R && py < d.ny; ++py) {
+        for (int px = max(2 * cx + 1 - R, 0); px <= 2 * cx + 1 + R && px < d.nx; ++px) {
+          const double wz = zweight_kind(kind, px, cx) * zweight_kind(kind, py, cy);
           const int cls = local_bc == 0 ? node_class(d.i0 + px, d.j0 + py, d.ax, d.bx, d.ay, d.by) : 4;
           for (int s = 0; s < kStencilPts; ++s) {
             const int fx = px + kSx[s], fy = py + kSy[s];
             if (fx < 0 || fx >= d.nx || fy < 0 || fy >= d.ny) continue;
-            const double wq = zweight(fx, qx) * zweight(fy, qy);
+            const double wq = zweight_kind(kind, fx, qx) * zweight_kind(kind, fy, qy);
             if (wq != 0.0) acc = acc + (wz * wq) * tab[cls * kStencilPts + s];
           }
         }
       }
     }
-    Ec[(d.coff + c) * 9 + o] = acc;
+    Ec[(d.coff + c) * K + o] = acc;
   }
 }
 
@@ -147,6 +150,69 @@ __global__ void __launch_bounds__(kBlock) factor_coarse_kernel(const SubDesc* __
     __syncthreads();
   }
   if (tid == 0) pivmin[blockIdx.x] = minp;
+}
+
+// Block LU over pairs of coarse rows (Bezier deflation, see coarse.hpp).  Unknown k of
+// block row I is coarse node (k % mx, 2 I + k / mx); a row beyond my is an identity row.
+__device__ __forceinline__ cplx<double> paired_coef(const SubDesc& d, const cplx<double>* __restrict__ ec, int I,
+                                                    int k, int J, int kk) {
+  const int x = k % d.mx, y = 2 * I + k / d.mx;
+  const int xx = kk % d.mx, yy = 2 * J + kk / d.mx;
+  if (y >= d.my || yy >= d.my) return (y == yy && x == xx) ? cplx<double>{1.0, 0.0} : czero<double>();
+  const int dx = xx - x, dy = yy - y;
+  if (dx < -2 || dx > 2 || dy < -2 || dy > 2) return czero<double>();
+  return ec[(size_t)(y * d.mx + x) * 25 + 5 * (dy + 2) + (dx + 2)];
+}
+
+__global__ void __launch_bounds__(kBlock) factor_coarse_paired_kernel(const SubDesc* __restrict__ subs,
+                                                                       const cplx<double>* __restrict__ Ec,
+                                                                       cplx<double>* __restrict__ fac,
+                                                                       double* __restrict__ pivmin) {
+  const SubDesc d = subs[blockIdx.x];
+  __shared__ int perm[kMaxMx];
+  __shared__ cplx<double> colp[kMaxMx];
+  __shared__ double pivabs;
+  const int bm = d.bmx, bn = d.bmy, mm = bm * bm, tid = threadIdx.x;
+  const cplx<double>* ec = Ec + d.coff * 25;
+  cplx<double>* F = fac + d.goff;
+  double minp = 1e300;
+  for (int I = 0; I < bn; ++I) {
+    cplx<double>* G = F + (size_t)I * mm;
+    cplx<double>* Lb = F + (size_t)(2 * bn - 2 + I) * mm;   // L_I (I >= 1)
+    const cplx<double>* Hprev = F + (size_t)(bn + I - 1) * mm;
+    if (I > 0) {
+      for (int e = tid; e < mm; e += blockDim.x) Lb[e] = paired_coef(d, ec, I, e / bm, I - 1, e % bm);
+      __syncthreads();
+    }
+    // S_I = D_I - L_I H_{I-1}
+    for (int e = tid; e < mm; e += blockDim.x) {
+      const int r = e / bm, c = e - r * bm;
+      cplx<double> s = paired_coef(d, ec, I, r, I, c);
+      if (I > 0)
+        for (int k = 0; k < bm; ++k) s = s - Lb[r * bm + k] * Hprev[k * bm + c];
+      G[e] = s;
+    }
+    __syncthreads();
+    minp = fmin(minp, gauss_jordan_inverse(G, bm, perm, colp, &pivabs));
+    if (I < bn - 1) {
+      // H_I = G_I U_I
+      cplx<double>* H = F + (size_t)(bn + I) * mm;
+      for (int e = tid; e < mm; e += blockDim.x) {
+        const int r = e / bm, c = e - r * bm;
+        cplx<double> s = czero<double>();
+        for (int k = 0; k < bm; ++k) s = s + G[r * bm + k] * paired_coef(d, ec, I, k, I + 1, c);
+        H[e] = s;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) pivmin[blockIdx.x] = minp;
+}
+
+hipError_t launch_factor_coarse_paired(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
+                                       double* pivmin, hipStream_t st) {
+  hipLaunchKernelGGL(factor_coarse_paired_kernel, dim3(nsub), dim3(kBlock), 0, st, subs, Ec, fac, pivmin);
+  return hipGetLastError();
 }
 
 hipError_t launch_assemble_coarse(const SubDesc* subs, int nsub, Consts cs, int local_bc, cplx<double>* Ec,

@@ -77,4 +77,23 @@ __host__ __device__ __forceinline__ double zweight(int i, int c) {
   return d == 0 ? 1.0 : ((d == 1 || d == -1) ? 0.5 : 0.0);
 }
 
+// Deflation vectors per direction (Sec. 2, eq. 5): linear interpolation, or the
+// quadratic rational Bezier stencil 1/8 [1 4 6 4 1] centred on fine node 2c+1 (the
+// printed map from fine to coarse values, read as Z^T).  zreach: largest distance from
+// 2c+1 with a non-zero weight, which is also the coupling radius of E = Z^T B Z.
+enum DeflationKind { kLinear = 0, kBezier = 1 };
+__host__ __device__ __forceinline__ int zreach(int kind) { return kind == kBezier ? 2 : 1; }
+__host__ __device__ __forceinline__ double zweight_kind(int kind, int i, int c) {
+  int d = i - (2 * c + 1);
+  d = d < 0 ? -d : d;
+  if (kind == kBezier) return d == 0 ? 0.75 : (d == 1 ? 0.5 : (d == 2 ? 0.125 : 0.0));
+  return d == 0 ? 1.0 : (d == 1 ? 0.5 : 0.0);
+}
+// Coefficients of E stored per coarse node: (2 zreach + 1)^2, neighbour (cx+dx, cy+dy) at
+// (2 zreach + 1)(dy + zreach) + (dx + zreach).
+__host__ __device__ __forceinline__ int coarse_coefs(int kind) {
+  const int w = 2 * zreach(kind) + 1;
+  return w * w;
+}
+
 }  // namespace ddh

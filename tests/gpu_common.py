@@ -9,9 +9,9 @@ from paper_2103_17081_amd import inputs
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_for(name: str, local_bc: str = "robin"):
+def oracle_for(name: str, local_bc: str = "robin", deflation: str = "linear"):
     w = inputs.workload(name)
-    return w, schwarz.Schwarz(schwarz.problem_from_workload(w, local_bc=local_bc))
+    return w, schwarz.Schwarz(schwarz.problem_from_workload(w, local_bc=local_bc, deflation=deflation))
 
 
 def solver_for(name: str, precision: int = 64, local_bc: str = "impedance", **kw):

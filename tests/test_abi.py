@@ -32,7 +32,7 @@ def test_default_params():
 @pytest.mark.parametrize("kw,needle", [
     (dict(overlap=0), "overlap"),
     (dict(k=-1.0), "k must"),
-    (dict(deflation="bezier"), "linear deflation"),
+    (dict(deflation=2), "deflation must be"),
     (dict(inner_precision=16), "inner_precision"),
     (dict(n_intervals=32, px=2, cuts_x=[0, 16, 31]), "cut points"),
     (dict(n_intervals=32, px=3, cuts_x=[0, 20, 20, 32]), "strictly increasing"),
