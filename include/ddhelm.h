@@ -48,6 +48,7 @@ typedef enum {
 
 enum { DD_LOCAL_IMPEDANCE = 0, DD_LOCAL_DIRICHLET = 1 };
 enum { DD_DEFLATION_LINEAR = 0, DD_DEFLATION_BEZIER = 1 };
+enum { DD_LOCAL_DEFLATED_GMRES = 0, DD_LOCAL_DIRECT = 1 };
 
 /* Problem and solver parameters.  Start from dd_default_params(). */
 typedef struct {
@@ -74,6 +75,10 @@ typedef struct {
   int nrhs;            /* independent right-hand sides solved together */
   int use_graph;       /* 1: outer steps replayed from a captured hipGraph (default), 0: launched one by one */
   int graph_steps;     /* outer steps per graph replay; convergence is read back once per replay */
+  int local_solver;    /* DD_LOCAL_DEFLATED_GMRES (default): inexact deflated-GMRES subdomain solves;
+                          DD_LOCAL_DIRECT: exact solves with the FP64 block LU of each local matrix
+                          (the direct-solve baseline of Sec. 3, Table 1); needs inner_precision 64,
+                          ignores the inner tolerances and the deflation choice */
 } dd_params;
 
 typedef struct {

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "DD_OK", 1: "DD_EINVAL", 2: "DD_ENOMEM", 3: "DD_EHIP", 4: "DD
                 5: "DD_ENOTCONV", 6: "DD_EWEIGHTS"}
 LOCAL_BC = {"impedance": 0, "robin": 0, "dirichlet": 1}
 DEFLATION = {"linear": 0, "bezier": 1}
+LOCAL_SOLVER = {"deflated": 0, "deflated_gmres": 0, "direct": 1}
 
 
 class Params(ctypes.Structure):
@@ -47,6 +48,7 @@ class Params(ctypes.Structure):
         ("nrhs", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("graph_steps", ctypes.c_int),
+        ("local_solver", ctypes.c_int),
     ]
 
 
@@ -215,7 +217,8 @@ class Solver:
                  cuts_x=None, cuts_y=None, overlap: int = 1, local_bc: str = "impedance",
                  deflation: str = "linear", inner_precision: int = 64, inner_tol: float = 1e-2,
                  inner_maxit: int = 100, outer_tol: float = 1e-6, outer_maxit: int = 3000,
-                 outer_restart: int = 0, nrhs: int = 1, use_graph: bool = True, graph_steps: int = 8):
+                 outer_restart: int = 0, nrhs: int = 1, use_graph: bool = True, graph_steps: int = 8,
+                 local_solver: str = "deflated"):
         p = default_params()
         p.k, p.ppwl, p.n_intervals = k, ppwl, n_intervals
         p.px, p.py = px, py
@@ -237,6 +240,7 @@ class Solver:
         p.nrhs = nrhs
         p.use_graph = 1 if use_graph else 0
         p.graph_steps = graph_steps
+        p.local_solver = LOCAL_SOLVER[local_solver]
         self.params = p
         self._h = ctypes.c_void_p()
         torch = _torch()
@@ -511,6 +515,8 @@ def setup_status(**kw) -> tuple[int, str]:
             p.local_bc = LOCAL_BC[val] if isinstance(val, str) else val
         elif key == "deflation":
             p.deflation = DEFLATION[val] if isinstance(val, str) else val
+        elif key == "local_solver":
+            p.local_solver = LOCAL_SOLVER[val] if isinstance(val, str) else val
         else:
             setattr(p, key, val)
     h = ctypes.c_void_p()

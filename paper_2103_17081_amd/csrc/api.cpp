@@ -104,6 +104,12 @@ struct dd_handle {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   dd_net* net = nullptr;        // attached guess network (borrowed)
+  // exact local solves (local_solver == DD_LOCAL_DIRECT)
+  bool direct = false;
+  cplx<double>* ffac = nullptr; // block-LU factors of the local matrices
+  long long* foff = nullptr;    // [nsub] factor offsets
+  std::vector<long long> foff_h;
+  long long nffac = 0;
   std::vector<void*> allocs;
 
   template <typename T>
@@ -179,6 +185,10 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   if (p->deflation != DD_DEFLATION_LINEAR && p->deflation != DD_DEFLATION_BEZIER)
     return fail(DD_EINVAL, "deflation must be DD_DEFLATION_LINEAR or DD_DEFLATION_BEZIER");
   if (p->inner_precision != 64 && p->inner_precision != 32) return fail(DD_EINVAL, "inner_precision must be 64 or 32");
+  if (p->local_solver != DD_LOCAL_DEFLATED_GMRES && p->local_solver != DD_LOCAL_DIRECT)
+    return fail(DD_EINVAL, "local_solver must be DD_LOCAL_DEFLATED_GMRES or DD_LOCAL_DIRECT");
+  if (p->local_solver == DD_LOCAL_DIRECT && p->inner_precision != 64)
+    return fail(DD_EINVAL, "direct local solves are FP64: inner_precision must be 64");
   if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return fail(DD_EINVAL, "inner_tol must be in (0, 1)");
   if (p->inner_maxit < 1 || p->inner_maxit > 1000) return fail(DD_EINVAL, "inner_maxit must be in [1, 1000]");
   if (!(p->outer_tol > 0.0 && p->outer_tol < 1.0)) return fail(DD_EINVAL, "outer_tol must be in (0, 1)");
@@ -211,7 +221,9 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   const int ov = p->overlap;
   const bool imp = p->local_bc == DD_LOCAL_IMPEDANCE;
   h->subs_h.clear();
-  long long off = 0, coff = 0, goff = 0;
+  h->direct = p->local_solver == DD_LOCAL_DIRECT;
+  h->foff_h.clear();
+  long long off = 0, coff = 0, goff = 0, foff = 0;
   for (int qy = 0; qy < p->py; ++qy) {
     for (int qx = 0; qx < p->px; ++qx) {
       SubDesc d{};
@@ -240,6 +252,11 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
       d.ncp = d.bmx * d.bmy;
       if (d.bmx > ddh::kMaxMx)
         return fail(DD_EINVAL, "subdomain too wide for the coarse kernels (coarse block size > 128)");
+      if (h->direct) {
+        if (d.nx > ddh::kMaxMx) return fail(DD_EINVAL, "subdomain too wide for direct local solves (nx > 128)");
+        h->foff_h.push_back(foff);
+        foff += ddh::coarse_factor_size(d.nx, d.ny);
+      }
       d.robin = 0;
       if (imp) d.robin = (d.ax > 0 ? 1 : 0) | (d.bx < n ? 2 : 0) | (d.ay > 0 ? 4 : 0) | (d.by < n ? 8 : 0);
       d.off = off; d.coff = coff; d.goff = goff;
@@ -255,6 +272,7 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   h->nfine = off;
   h->ncoarse = coff;
   h->nfac = goff;
+  h->nffac = foff;
   h->cs.n = n;
   h->cs.nsub = h->nsub;
   h->cs.k = p->k;
@@ -269,7 +287,7 @@ dd_status check_lds(dd_handle* h) {
   int dev = 0, maxlds = 0;
   DD_HIP(hipGetDevice(&dev));
   DD_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  size_t need = ddh::inner_lds_bytes<T>(h->max_nj, h->max_nc, h->maxit);
+  size_t need = h->direct ? ddh::direct_lds_bytes(h->max_nj) : ddh::inner_lds_bytes<T>(h->max_nj, h->max_nc, h->maxit);
   if (need > (size_t)maxlds)
     return fail(DD_EINVAL, "subdomain tile too large for LDS (" + std::to_string(need) + " > " +
                                std::to_string(maxlds) + " bytes); use more subdomains or fewer inner iterations");
@@ -323,7 +341,7 @@ ddh::InnerArgs<T> inner_args(dd_handle* h) {
 // without a network).
 dd_status run_guess(dd_handle* h, const cplx<double>* r, long long rstride, const int* done, hipStream_t st,
                     const int* jdev = nullptr, long long rslot = 0) {
-  if (!h->net) return DD_OK;
+  if (!h->net || h->direct) return DD_OK;
   ddh::TileArgs ta{};
   ta.subs = h->subs;
   ta.cs = h->cs;
@@ -337,10 +355,37 @@ dd_status run_guess(dd_handle* h, const cplx<double>* r, long long rstride, cons
 
 // Batched subdomain solves: z = M^{-1} r over all right-hand sides (those with done set
 // are skipped), starting from the network's guess tiles when a network is attached.
+ddh::DirectArgs direct_args(dd_handle* h) {
+  ddh::DirectArgs a{};
+  a.subs = h->subs;
+  a.order = h->lpt ? h->order : nullptr;
+  a.cs = h->cs;
+  a.local_bc = h->p.local_bc;
+  a.ffac = h->ffac;
+  a.foff = h->foff;
+  a.iters = h->iters;
+  a.flags = h->flags;
+  a.counters = h->counters;
+  a.nfine = h->nfine;
+  a.ndof = h->ndof;
+  a.rstride = h->ndof;
+  a.zstride = h->ndof;
+  a.nrhs = h->nrhs;
+  a.max_nj = h->max_nj;
+  return a;
+}
+
 dd_status run_inner(dd_handle* h, const cplx<double>* r, long long rstride, cplx<double>* z, long long zstride,
                     const int* done, hipStream_t st, const int* jdev = nullptr, long long rslot = 0,
                     long long zslot = 0) {
-  const float* gt = h->net ? h->net->y : nullptr;
+  if (h->direct) {
+    auto a = direct_args(h);
+    a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot;
+    DD_HIP(ddh::launch_direct_solve(a, st));
+    return DD_OK;
+  }
+  const float* gt = h->net ? h->net->y : nullptr;   // (exact solves take no guess)
   const int gT = h->net ? h->net->T : 0;
   if (h->prec == 32) {
     auto a = inner_args<float>(h);
@@ -409,6 +454,37 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     for (int j = 0; j < h->nsub; ++j)
       if (!(h->pivmin_h[j] > 0.0) || !std::isfinite(h->pivmin_h[j]))
         return fail(DD_ESINGULAR, "coarse matrix E_" + std::to_string(j) + " is singular (zero pivot)");
+    if (h->direct) {
+      // block LU of every local matrix: its 9-coefficient form, factored by the same
+      // kernel as E through per-subdomain views (block size nx, ny block rows)
+      DD_TRY(h->alloc(&h->ffac, (size_t)h->nffac));
+      DD_TRY(h->alloc(&h->foff, h->nsub));
+      DD_HIP(hipMemcpy(h->foff, h->foff_h.data(), h->nsub * sizeof(long long), hipMemcpyHostToDevice));
+      std::vector<SubDesc> views(h->subs_h);
+      for (int j = 0; j < h->nsub; ++j) {
+        views[j].mx = views[j].nx;
+        views[j].my = views[j].ny;
+        views[j].coff = views[j].off;
+        views[j].goff = h->foff_h[j];
+      }
+      cplx<double>* Bc = nullptr;
+      SubDesc* vd = nullptr;
+      DD_HIP(hipMalloc((void**)&Bc, (size_t)h->nfine * 9 * sizeof(cplx<double>)));
+      hipError_t e = hipMalloc((void**)&vd, h->nsub * sizeof(SubDesc));
+      if (e == hipSuccess) e = hipMemcpy(vd, views.data(), h->nsub * sizeof(SubDesc), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = ddh::launch_fine_coef(h->subs, h->nsub, h->cs, h->p.local_bc, Bc, st);
+      if (e == hipSuccess) e = ddh::launch_factor_coarse(vd, h->nsub, Bc, h->ffac, h->pivmin, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(h->pivmin_h.data(), h->pivmin, h->nsub * sizeof(double),
+                                              hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      (void)hipFree(Bc);
+      if (vd) (void)hipFree(vd);
+      if (e != hipSuccess) return fail(DD_EHIP, std::string("direct factorisation: ") + hipGetErrorString(e));
+      for (int j = 0; j < h->nsub; ++j)
+        if (!(h->pivmin_h[j] > 0.0) || !std::isfinite(h->pivmin_h[j]))
+          return fail(DD_ESINGULAR, "local matrix B_" + std::to_string(j) + " is singular (zero pivot)");
+      DD_HIP(ddh::configure_direct(h->max_nj));
+    }
     if (h->prec == 32) DD_TRY(alloc_inner<float>(h));
     else DD_TRY(alloc_inner<double>(h));
     DD_TRY(h->alloc(&h->R, (size_t)h->nsub * h->nrhs * h->maxit * h->maxit));
@@ -941,7 +1017,12 @@ dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void
   hipStream_t st = (hipStream_t)stream;
   const size_t bytes = (size_t)h->nfine * h->nrhs * (h->prec == 32 ? 8 : 16);
   DD_HIP(hipMemcpyAsync(h->F, f, bytes, hipMemcpyDeviceToDevice, st));
-  if (h->prec == 32) {
+  if (h->direct) {
+    auto a = direct_args(h);
+    a.F = (const cplx<double>*)h->F;
+    a.U = (cplx<double>*)u;
+    DD_HIP(ddh::launch_direct_solve(a, st));
+  } else if (h->prec == 32) {
     auto a = inner_args<float>(h);
     a.guess = (const cplx<float>*)guess;
     a.U = (cplx<float>*)u;

@@ -67,14 +67,19 @@ __device__ __forceinline__ void stage_lower(const SubDesc& d, const cplx<double>
 
 namespace detail {
 
-// Fast path: lane l of group r owns columns c = l + q L (q < Q).  The factor entries
-// of kCoarseBatch consecutive steps are loaded together, in straight-line code with
-// clamped indices, before those steps run; memory latency is then paid once per
-// batch rather than once per step.
-template <int L, int Q>
-__device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<double>* __restrict__ F,
-                                                  const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
-  const int mx = d.mx, my = d.my, mm = mx * mx;
+// Block-tridiagonal solve with inverted diagonal blocks (the factor layout above), for
+// any operator whose lower coupling L_i is tridiagonal: lower(i, c, e) is the coupling
+// of unknown c of block row i to unknown c + e - 1 of block row i - 1 (e = 0, 1, 2).
+// Lane l of group r owns columns c = l + q L (q < Q).  The factor entries of Depth
+// consecutive steps are loaded together, in straight-line code with clamped indices,
+// before those steps run, so memory latency is paid once per batch rather than once per
+// step.  The coupled right-hand side t_i - L_i a_{i-1} is formed once per column
+// (threads 0..mx-1, in place in t) between the block products instead of by every row
+// group.
+template <int L, int Q, int Depth, typename Lower>
+__device__ __forceinline__ void block_solve_ring(int mx, int my, const cplx<double>* __restrict__ F, Lower lower,
+                                                 cplx<double>* t, cplx<double>* a) {
+  const int mm = mx * mx;
   const int r = threadIdx.x / L, l = threadIdx.x % L;
   const bool active = r < mx;
   int col[Q];
@@ -88,19 +93,17 @@ __device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<d
   int eoff[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) eoff[q] = ok[q] ? r * mx + col[q] : 0;
-  cplx<double> ring[kCoarseBatch][Q];
-  // forward: a_i = G_i (t_i - L_i a_{i-1}), G_i = block i.  The coupled right-hand side
-  // t_i - L_i a_{i-1} is formed once per column (threads 0..mx-1, in place in t) between
-  // the block products instead of by every row group.
-  for (int i0 = 0; i0 < my; i0 += kCoarseBatch) {
+  cplx<double> ring[Depth][Q];
+  // forward: a_i = G_i (t_i - L_i a_{i-1}), G_i = block i
+  for (int i0 = 0; i0 < my; i0 += Depth) {
 #pragma unroll
-    for (int u = 0; u < kCoarseBatch; ++u) {
+    for (int u = 0; u < Depth; ++u) {
       const int blk = min(i0 + u, my - 1);
 #pragma unroll
       for (int q = 0; q < Q; ++q) ring[u][q] = F[(size_t)blk * mm + eoff[q]];
     }
 #pragma unroll
-    for (int u = 0; u < kCoarseBatch; ++u) {
+    for (int u = 0; u < Depth; ++u) {
       const int i = i0 + u;
       if (i < my) {
         cplx<double> acc = czero<double>();
@@ -114,11 +117,10 @@ __device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<d
         if (i + 1 < my) {
           const int c = threadIdx.x;
           if (c < mx) {
-            const cplx<double>* cpl = lc + 3 * ((i + 1) * mx + c);
             const cplx<double>* ap = a + i * mx + c;
-            cplx<double> rhs = t[(i + 1) * mx + c] - cpl[1] * ap[0];
-            if (c > 0) rhs = rhs - cpl[0] * ap[-1];
-            if (c < mx - 1) rhs = rhs - cpl[2] * ap[1];
+            cplx<double> rhs = t[(i + 1) * mx + c] - lower(i + 1, c, 1) * ap[0];
+            if (c > 0) rhs = rhs - lower(i + 1, c, 0) * ap[-1];
+            if (c < mx - 1) rhs = rhs - lower(i + 1, c, 2) * ap[1];
             t[(i + 1) * mx + c] = rhs;
           }
           lds_barrier();
@@ -127,15 +129,15 @@ __device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<d
     }
   }
   // backward: y_i = a_i - H_i y_{i+1}, H_i = block my + i, i = my-2 .. 0
-  for (int i0 = my - 2; i0 >= 0; i0 -= kCoarseBatch) {
+  for (int i0 = my - 2; i0 >= 0; i0 -= Depth) {
 #pragma unroll
-    for (int u = 0; u < kCoarseBatch; ++u) {
+    for (int u = 0; u < Depth; ++u) {
       const int blk = my + max(i0 - u, 0);
 #pragma unroll
       for (int q = 0; q < Q; ++q) ring[u][q] = F[(size_t)blk * mm + eoff[q]];
     }
 #pragma unroll
-    for (int u = 0; u < kCoarseBatch; ++u) {
+    for (int u = 0; u < Depth; ++u) {
       const int i = i0 - u;
       if (i >= 0) {
         cplx<double> acc = czero<double>();
@@ -151,11 +153,20 @@ __device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<d
   }
 }
 
-// General path for any mx <= kMaxMx: no prefetch, shuffle reductions.
-template <int NT>
-__device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<double>* __restrict__ F,
-                                                   const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
-  const int mx = d.mx, my = d.my, mm = mx * mx;
+// Coarse solve through the ring with E's lower couplings staged in LDS (lc).
+template <int L, int Q>
+__device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<double>* __restrict__ F,
+                                                  const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
+  auto lower = [lc, mx = d.mx](int i, int c, int e) { return lc[3 * (i * mx + c) + e]; };
+  block_solve_ring<L, Q, kCoarseBatch>(d.mx, d.my, F, lower, t, a);
+}
+
+// General path for any mx <= kMaxMx: no prefetch, shuffle reductions over groups of
+// L lanes (lower couplings as in block_solve_ring).
+template <int NT, typename Lower>
+__device__ __forceinline__ void block_solve_plain(int mx, int my, const cplx<double>* __restrict__ F, Lower lower,
+                                                  cplx<double>* t, cplx<double>* a) {
+  const int mm = mx * mx;
   const int L = coarse_group_lanes<NT>(mx);
   const int r = threadIdx.x / L, l = threadIdx.x % L;
   const bool active = r < mx;
@@ -174,7 +185,7 @@ __device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<
         if (i > 0) {
           for (int e = 0; e < 3; ++e) {
             const int cc = c + e - 1;
-            if (cc >= 0 && cc < mx) rhs = rhs - lc[3 * (i * mx + c) + e] * a[(i - 1) * mx + cc];
+            if (cc >= 0 && cc < mx) rhs = rhs - lower(i, c, e) * a[(i - 1) * mx + cc];
           }
         }
         acc = cfma(F[(size_t)i * mm + r * mx + c], rhs, acc);
@@ -192,6 +203,13 @@ __device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<
     if (active && l == 0) a[i * mx + r] = a[i * mx + r] - acc;
     lds_barrier();
   }
+}
+
+template <int NT>
+__device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<double>* __restrict__ F,
+                                                   const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
+  auto lower = [lc, mx = d.mx](int i, int c, int e) { return lc[3 * (i * mx + c) + e]; };
+  block_solve_plain<NT>(d.mx, d.my, F, lower, t, a);
 }
 
 // Paired-row (Bezier) block solve with dense lower couplings; shuffle reductions over

@@ -83,6 +83,33 @@ template <typename T>
 hipError_t launch_scatter(const SubDesc* subs, int nsub, Consts cs, const cplx<T>* u, cplx<double>* z,
                           long long nfine, long long ndof, int nrhs, hipStream_t st);
 
+// ---- exact subdomain solves (FP64 block LU of the local matrices) ---------------------
+struct DirectArgs {
+  const SubDesc* subs;
+  const int* order;              // launch order (size nsub * nrhs) or null
+  Consts cs;
+  int local_bc;
+  const cplx<double>* ffac;      // block-LU factors of the local matrices
+  const long long* foff;         // [nsub] factor offsets (complex<double> elements)
+  const cplx<double>* r;         // global right-hand sides, or null: use F
+  cplx<double>* z;               // global output (owned nodes), or null
+  const cplx<double>* F;         // packed right-hand sides [nrhs][nfine]
+  cplx<double>* U;               // packed solutions, or null
+  const int* done;
+  int* iters;                    // [nrhs][nsub] set to 0, or null
+  int* flags;                    // [nrhs][nsub] set to 0, or null
+  unsigned long long* counters;  // [5] as InnerArgs: [1] solves, [4] algorithmic bytes
+  long long nfine, ndof, rstride, zstride;
+  const int* jdev;
+  long long rslot, zslot;
+  int nrhs, max_nj;
+};
+hipError_t launch_fine_coef(const SubDesc* subs, int nsub, Consts cs, int local_bc, cplx<double>* Bc,
+                            hipStream_t st);
+hipError_t launch_direct_solve(const DirectArgs& a, hipStream_t st);
+size_t direct_lds_bytes(int max_nj);
+hipError_t configure_direct(int max_nj);
+
 // ---- global FP64 operations (outer FGMRES) -----------------------------------------
 hipError_t launch_global_apply(Consts cs, const cplx<double>* v, cplx<double>* w, int nrhs, hipStream_t st);
 

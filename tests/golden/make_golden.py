@@ -2,12 +2,14 @@
 
 Usage: python tests/golden/make_golden.py small [medium] [large]
        python tests/golden/make_golden.py --spread small [medium]
+       python tests/golden/make_golden.py --direct small [medium] [large]
 
 For each named workload (paper_2103_17081_amd.inputs.workload) and its first right-hand
 side, runs the oracle's outer FGMRES with impedance (ORAS) local matrices, linear
 deflation and deflated-GMRES subdomain solves at the workload's inner tolerance, and
 records the outer count, total inner iterations, subdomain solves and the true relative
-residual.  Existing entries for other workloads are kept.
+residual.  Existing entries for other workloads are kept.  --direct records, under
+"direct", the same run with exact (sparse LU) subdomain solves.
 """
 
 import json
@@ -84,9 +86,25 @@ def main(names):
             json.dump(data, fh, indent=1, sort_keys=True)
 
 
+def direct(names):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name in names:
+        w = inputs.workload(name)
+        S = schwarz.Schwarz(schwarz.problem_from_workload(w))
+        t = time.time()
+        _, st = S.solve(w.rhs[0], mode="direct", outer_maxit=5000)
+        data.setdefault(name, {})["direct"] = {"outer_iters": st.outer_iters, "true_relres": st.true_relres,
+                                               "oracle_seconds": round(time.time() - t, 1)}
+        print(name, data[name]["direct"], flush=True)
+        with open(OUT, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
-    if args and args[0] == "--spread":
+    if args and args[0] == "--direct":
+        direct(args[1:] or ["small"])
+    elif args and args[0] == "--spread":
         data = json.load(open(OUT)) if os.path.exists(OUT) else {}
         for name in args[1:] or ["small"]:
             data.setdefault(name, {})["fp32_perturbed_outer"] = spread(name, 8 if name == "small" else 2)

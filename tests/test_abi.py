@@ -41,6 +41,8 @@ def test_default_params():
     (dict(outer_maxit=0), "outer_maxit"),
     (dict(n_intervals=32, px=33), "subdomain counts"),
     (dict(n_intervals=8, px=8, local_bc="dirichlet"), "2 x 2"),
+    (dict(local_solver="direct", inner_precision=32), "direct local solves are FP64"),
+    (dict(local_solver=5), "local_solver must be"),
 ])
 def test_invalid_parameters_rejected_on_host(kw, needle):
     st, msg = binding.setup_status(**kw)
