@@ -16,7 +16,9 @@ library) over durations from HIP events recorded on the library's stream around 
 kernel, in one more solve of the same handle and inputs with the steps launched one
 by one right after the timed solves (HIP cannot time events inside graph replays);
 `roofline` is the one with the largest total time.  The CPU baseline is the oracle timed on a
-bounded sample of the same workload (its first outer iterations).
+bounded sample of the same workload (its first outer iterations).  `direct_local_solves`
+times the same solve with exact subdomain solves (FP64 block LU of every local matrix, the
+direct-solve baseline of the paper's experiments) for comparison.
 """
 
 from __future__ import annotations
@@ -60,6 +62,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
     ap.add_argument("--no-plain", action="store_true", help="skip the all-FP64 comparison solve")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the comparison with exact (FP64 block-LU) subdomain solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-outer", type=int, default=40, help="outer iterations of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -67,11 +71,11 @@ def parse():
     return ap.parse_args()
 
 
-def make_solver(w, precision: int):
+def make_solver(w, precision: int, local_solver: str = "deflated"):
     from paper_2103_17081_amd.binding import Solver
     return Solver(w.k, n_intervals=w.n, cuts_x=w.cuts_x, cuts_y=w.cuts_y, overlap=w.overlap,
                   inner_precision=precision, inner_tol=w.inner_tol, outer_tol=w.outer_tol,
-                  outer_maxit=4000)
+                  outer_maxit=4000, local_solver=local_solver)
 
 
 def true_relres(torch, solver, f, u):
@@ -197,6 +201,20 @@ def main():
                         "graph_replays": sp[-1]["graph_replays"]}
         out["chosen_speedup_vs_plain"] = tp / (t / args.steps)
         plain.close()
+    if not args.no_direct:
+        # the paper's direct-solve baseline: exact FP64 subdomain solves (block LU of each B_j)
+        direct = make_solver(w, 64, "direct")
+        td, ud, sd = timed_solves(torch, direct, f, 1, 1)
+        direct.set_graph(False)
+        _, di = direct.solve(f)
+        torch.cuda.synchronize()
+        out["direct_local_solves"] = {
+            "time_to_solution_s": td, "outer_iters": sd[-1]["outer_iters"],
+            "subdomain_solves_per_s": sd[-1]["subdomain_solves"] / td,
+            "true_relres": true_relres(torch, direct, f, ud), "status": sd[-1]["status"],
+            "ms_per_precond_apply": di["ms_inner"] / max(di["precond_applies"], 1),
+            "algorithmic_GB_per_apply": di["inner_bytes"] / max(di["precond_applies"], 1) / 1e9}
+        direct.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_outer)
     print(json.dumps(out), flush=True)
