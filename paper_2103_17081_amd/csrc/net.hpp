@@ -122,7 +122,7 @@ struct TileArgs {
 
 hipError_t launch_net_prepare(const NetTable& nt, const float* params, bf16x8* frags, hipStream_t st);
 hipError_t launch_conv(const ConvArgs& a, int batch, hipStream_t st);
-size_t conv_lds_bytes(int H, int W, int cinp, int nb);
+size_t conv_lds_bytes(int H, int W, int cinp, int nb, int ksteps);
 hipError_t launch_conv_wgrad(const ConvArgs& a, const bf16* dz, int cout, int batch, float* part, float* bpart,
                              hipStream_t st);
 size_t wgrad_lds_bytes(int H, int W, int cinp, int cout);

@@ -57,27 +57,71 @@ __device__ __forceinline__ bf16x8 load_input(const ConvArgs& a, int b, int y, in
   return *(const bf16x8*)(a.x1 + (((size_t)b * H + y) * W + x) * cs + (ch - a.c1));
 }
 
+constexpr int kStageBatch = 8;   // staging loads each thread keeps in flight
+
 // Rows y0-1 .. y0+rows of tile b, columns -1 .. W, into LDS (pixel stride cinp + 8).
+// Each thread issues kStageBatch loads before storing any, so the band arrives in a few
+// memory latencies rather than one per unit.
 __device__ __forceinline__ void stage_input(const ConvArgs& a, int b, int y0, int rows, bf16* lds) {
   const int W = a.W, cg = a.cinp >> 3, ps = a.cinp + 8, W2 = W + 2;
   const int units = (rows + 2) * W2 * cg;
-  for (int u = threadIdx.x; u < units; u += blockDim.x) {
-    const int g = u % cg, pc = u / cg;
-    const int c = pc % W2, r = pc / W2;
-    const int y = y0 - 1 + r, x = c - 1;
-    bf16x8 v = zero8();
-    if (y >= 0 && y < a.H && x >= 0 && x < W) v = load_input(a, b, y, x, g * 8);
-    *(bf16x8*)(lds + (size_t)pc * ps + g * 8) = v;
+  const int nt = blockDim.x;
+  for (int u0 = threadIdx.x; u0 < units; u0 += nt * kStageBatch) {
+    bf16x8 v[kStageBatch];
+#pragma unroll
+    for (int q = 0; q < kStageBatch; ++q) {
+      const int u = u0 + q * nt;
+      v[q] = zero8();
+      if (u < units) {
+        const int g = u % cg, pc = u / cg;
+        const int c = pc % W2, r = pc / W2;
+        const int y = y0 - 1 + r, x = c - 1;
+        if (y >= 0 && y < a.H && x >= 0 && x < W) v[q] = load_input(a, b, y, x, g * 8);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kStageBatch; ++q) {
+      const int u = u0 + q * nt;
+      if (u < units) {
+        const int g = u % cg, pc = u / cg;
+        *(bf16x8*)(lds + (size_t)pc * ps + g * 8) = v[q];
+      }
+    }
+  }
+}
+
+// n bf16x8 values from global to LDS, kStageBatch loads in flight per thread.
+__device__ __forceinline__ void stage_copy(const bf16x8* __restrict__ src, bf16x8* dst, int n) {
+  const int nt = blockDim.x;
+  for (int u0 = threadIdx.x; u0 < n; u0 += nt * kStageBatch) {
+    bf16x8 v[kStageBatch];
+#pragma unroll
+    for (int q = 0; q < kStageBatch; ++q) v[q] = u0 + q * nt < n ? src[u0 + q * nt] : zero8();
+#pragma unroll
+    for (int q = 0; q < kStageBatch; ++q)
+      if (u0 + q * nt < n) dst[u0 + q * nt] = v[q];
   }
 }
 
 }  // namespace
 
-size_t conv_lds_bytes(int H, int W, int cinp, int nb) {
-  const int mf = nb >= 8 ? 2 : 4;
+// LDS of one 3x3 product with MF fragments per wave: the staged input band (rounded up
+// to 16 bytes) followed by all weight fragments of the layer.
+static size_t conv_lds_bytes_mf(int H, int W, int cinp, int nb, int ksteps, int mf) {
   const int np = std::min(64 * mf, H * W);
   const int rows = (np + W - 1) / W;
-  return (size_t)(rows + 2) * (W + 2) * (cinp + 8) * sizeof(bf16);
+  const size_t in = ((size_t)(rows + 2) * (W + 2) * (cinp + 8) * sizeof(bf16) + 15) & ~size_t(15);
+  return in + (size_t)ksteps * nb * 64 * sizeof(bf16x8);
+}
+
+// Fragments per wave: 4 unless that band plus the weights exceed the LDS.
+static int conv_mf(int H, int W, int cinp, int nb, int ksteps) {
+  if (nb >= 8) return 2;
+  return conv_lds_bytes_mf(H, W, cinp, nb, ksteps, 4) <= 160 * 1024 ? 4 : 2;
+}
+
+size_t conv_lds_bytes(int H, int W, int cinp, int nb, int ksteps) {
+  return conv_lds_bytes_mf(H, W, cinp, nb, ksteps, conv_mf(H, W, cinp, nb, ksteps));
 }
 
 // out[p][co] = bias[co] + sum_{tap, ci} in[p + off(tap)][ci] W[tap][ci][co]   (+ relu)
@@ -92,6 +136,11 @@ __global__ void __launch_bounds__(kNetThreads) conv3x3_kernel(ConvArgs a) {
   const int np = min(64 * MF, npix - p0);
   const int y0 = p0 >> a.lw, rows = ((p0 + np - 1) >> a.lw) - y0 + 1;
   stage_input(a, b, y0, rows, lds);
+  // all weight fragments of the layer, after the input band (whose LDS size is that of
+  // the first block, the largest)
+  const int rows0 = (min(64 * MF, npix) + W - 1) / W;
+  bf16x8* lwf = (bf16x8*)(smem + ((((size_t)(rows0 + 2) * (W + 2) * (a.cinp + 8) * sizeof(bf16)) + 15) & ~size_t(15)));
+  stage_copy(a.wf, lwf, a.ksteps * NB * 64);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
   const int ps = a.cinp + 8, W2 = W + 2;
@@ -105,7 +154,6 @@ __global__ void __launch_bounds__(kNetThreads) conv3x3_kernel(ConvArgs a) {
     const int py = p >> a.lw, px = p & (W - 1);
     pofs[f] = ((py - y0 + 1) * W2 + px + 1) * ps;
   }
-  const bf16x8* __restrict__ wf = a.wf;
   for (int ks = 0; ks < a.ksteps; ++ks) {
     const int k0 = ks * 32 + lg * 8;
     const int tap = k0 / a.cinp, ch = k0 - tap * a.cinp;
@@ -113,7 +161,7 @@ __global__ void __launch_bounds__(kNetThreads) conv3x3_kernel(ConvArgs a) {
     const int toff = tv ? ((tap / 3 - 1) * W2 + (tap % 3 - 1)) * ps + ch : 0;
     bf16x8 wv[NB];
 #pragma unroll
-    for (int n = 0; n < NB; ++n) wv[n] = wf[((size_t)ks * NB + n) * 64 + lane];
+    for (int n = 0; n < NB; ++n) wv[n] = lwf[(ks * NB + n) * 64 + lane];
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
       if ((wave + 4 * f) * 16 < np) {
@@ -151,15 +199,25 @@ __global__ void __launch_bounds__(kNetThreads) conv3x3_kernel(ConvArgs a) {
 
 hipError_t launch_conv(const ConvArgs& a, int batch, hipStream_t st) {
   const int npix = a.H * a.W;
-  const int mf = a.nb >= 8 ? 2 : 4;
+  const int mf = conv_mf(a.H, a.W, a.cinp, a.nb, a.ksteps);
   const dim3 grid((npix + 64 * mf - 1) / (64 * mf), batch);
-  const size_t lds = conv_lds_bytes(a.H, a.W, a.cinp, a.nb);
-  switch (a.nb) {
-    case 1: hipLaunchKernelGGL((conv3x3_kernel<1, 4>), grid, dim3(kNetThreads), lds, st, a); break;
-    case 2: hipLaunchKernelGGL((conv3x3_kernel<2, 4>), grid, dim3(kNetThreads), lds, st, a); break;
-    case 4: hipLaunchKernelGGL((conv3x3_kernel<4, 4>), grid, dim3(kNetThreads), lds, st, a); break;
-    case 8: hipLaunchKernelGGL((conv3x3_kernel<8, 2>), grid, dim3(kNetThreads), lds, st, a); break;
-    default: return hipErrorInvalidValue;
+  const size_t lds = conv_lds_bytes_mf(a.H, a.W, a.cinp, a.nb, a.ksteps, mf);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (mf == 4) {
+    switch (a.nb) {
+      case 1: hipLaunchKernelGGL((conv3x3_kernel<1, 4>), grid, dim3(kNetThreads), lds, st, a); break;
+      case 2: hipLaunchKernelGGL((conv3x3_kernel<2, 4>), grid, dim3(kNetThreads), lds, st, a); break;
+      case 4: hipLaunchKernelGGL((conv3x3_kernel<4, 4>), grid, dim3(kNetThreads), lds, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (a.nb) {
+      case 1: hipLaunchKernelGGL((conv3x3_kernel<1, 2>), grid, dim3(kNetThreads), lds, st, a); break;
+      case 2: hipLaunchKernelGGL((conv3x3_kernel<2, 2>), grid, dim3(kNetThreads), lds, st, a); break;
+      case 4: hipLaunchKernelGGL((conv3x3_kernel<4, 2>), grid, dim3(kNetThreads), lds, st, a); break;
+      case 8: hipLaunchKernelGGL((conv3x3_kernel<8, 2>), grid, dim3(kNetThreads), lds, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
@@ -683,6 +741,12 @@ hipError_t configure_net() {
   if ((e = hipFuncSetAttribute((const void*)conv3x3_kernel<4, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim)))
     return e;
   if ((e = hipFuncSetAttribute((const void*)conv3x3_kernel<8, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)conv3x3_kernel<1, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)conv3x3_kernel<2, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim)))
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)conv3x3_kernel<4, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim)))
     return e;
   return hipFuncSetAttribute((const void*)conv3x3_wgrad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
