@@ -274,3 +274,32 @@ def test_dirichlet_local_variant(torch, prec):
         assert rel <= 1e-6
         if prec == 64:
             assert abs(st["outer_iters"] - ost.outer_iters) <= 1
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_xlarge_multi_rhs_sampled(torch, prec):
+    """The largest one-GPU configuration at full size: k=400, N=1274 (1.62M unknowns), 32x32
+    uneven subdomains, 8 right-hand sides in one launch.  One preconditioner application
+    on 8 random residuals; 8 sampled (subdomain, right-hand side) solves recomputed one by
+    one by the oracle (only the sampled subdomains are assembled on the CPU)."""
+    _case("xlarge sampled apply", prec)
+    from oracle import partition, schwarz
+    from paper_2103_17081_amd import inputs
+    w = inputs.workload("xlarge")
+    nrhs = len(w.rhs)
+    prob = schwarz.problem_from_workload(w)
+    geoms = partition.subdomains(prob.n, prob.cuts_x, prob.cuts_y, prob.overlap, prob.local_bc)
+    with solver_for("xlarge", precision=prec, nrhs=nrhs, outer_maxit=10) as gpu:
+        rng = np.random.default_rng(15)
+        r = np.stack([crandn(rng, gpu.ndof) for _ in range(nrhs)])
+        z = to_np(gpu.apply_preconditioner(to_gpu(torch, r)))
+        assert z.shape == (nrhs, gpu.ndof) and np.all(np.isfinite(z))
+        tol = 1e-8 if prec == 64 else 2e-3
+        for _ in range(8):
+            j, q = int(rng.integers(len(geoms))), int(rng.integers(nrhs))
+            g = geoms[j]
+            s = schwarz.Subdomain(prob, g)
+            ur, _, _ = s.deflated_gmres(r[q][g.idx], w.inner_tol, 100)
+            ref = ur[g.owned]
+            err = np.linalg.norm(z[q][g.idx[g.owned]] - ref) / np.linalg.norm(ref)
+            assert err <= tol, (j, q, err)
