@@ -20,6 +20,9 @@ krylov     GMRES with modified Gram-Schmidt and Givens rotations; right-flexible
            FGMRES (Sec. 3).
 schwarz    Restricted additive Schwarz preconditioner (eq. 3) with direct or
            deflated-GMRES subdomain solves, and the outer FGMRES driver.
+coarse_space  Two-level variant (the step after the one-level method, Sec. 4): a global
+           coarse space of piecewise-linear hats on a coarse grid of fine-grid lines,
+           E_0 = Z_0^T A Z_0, and the deflation-type combination with eq. 3.
 cnn        float64 reference of the learned-initial-guess network (forward and
            backward), checked against finite differences.
 
