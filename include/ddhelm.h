@@ -79,6 +79,15 @@ typedef struct {
                           DD_LOCAL_DIRECT: exact solves with the FP64 block LU of each local matrix
                           (the direct-solve baseline of Sec. 3, Table 1); needs inner_precision 64,
                           ignores the inner tolerances and the deflation choice */
+  int coarse_intervals; /* 0 (default): the one-level preconditioner of eq. 3.  M >= 2: two-level
+                          method with a global coarse space, the extension the paper's
+                          conclusions propose (Sec. 4): coarse grid lines at fine indices
+                          p_c = floor(c N / M + 1/2), c = 0..M; Z_0 = Z^y kron Z^x with the
+                          piecewise-linear hats of the interior lines (the global analogue of the
+                          linear deflation of eq. 5); E_0 = Z_0^T A Z_0 factored exactly (FP64
+                          block cyclic reduction); each application is
+                          M^{-1} r = M_1^{-1} (r - A Q_0 r) + Q_0 r, Q_0 = Z_0 E_0^{-1} Z_0^T, with
+                          M_1^{-1} the one-level preconditioner.  Needs M <= N and M - 1 <= 512. */
 } dd_params;
 
 typedef struct {
@@ -102,8 +111,8 @@ typedef struct {
   int inner_launches;          /* outer steps enqueued (including no-op steps after convergence
                                   inside a graph replay) */
   /* Algorithmic bytes of the subdomain-solve kernel summed over its launches: per solve,
-     gather 16 n_j + scatter 16 owned_j + (k_j + 2) coarse-factor reads of
-     16 ((2 my - 1) mx^2 + 3 mx my) bytes + Krylov traffic s n_j (2 k_j + 2 k_j (k_j + 1))
+     gather 16 n_j + scatter 16 owned_j (32 when the two-level correction is added) +
+     (k_j + 2) coarse-factor reads of 16 ((2 my - 1) mx^2 + 3 mx my) bytes + Krylov traffic s n_j (2 k_j + 2 k_j (k_j + 1))
      (basis writes, CGS2 reads, final combination) + local rhs write/read 2 s n_j, with
      s = 8 (FP32) or 16 bytes per complex value. */
   double inner_bytes;
@@ -119,6 +128,10 @@ typedef struct {
   double ms_steps;             /* all outer steps, from events around each replay or batch */
   double ms_guess;             /* network input tiles + forward pass of an attached guess network
                                   (timed outer steps only; 0 without a network) */
+  double ms_coarse;            /* two-level coarse correction: restriction, coarse solve, Z_0 x and
+                                  r - A Z_0 x (timed outer steps only; 0 for the one-level method) */
+  double coarse_bytes;         /* factor and vector bytes one coarse solve reads and writes (the
+                                  algorithmic traffic of the block cyclic reduction); 0 without it */
 } dd_stats;
 
 /* Fill *p with the defaults: k = 20, ppwl = 10, 2 x 2 uniform subdomains, overlap 1,
@@ -135,7 +148,8 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out);
 
 /* z = M^{-1} r = sum_j R_j^T D_j u_j (Sec. 2, eq. 3), every u_j an inexact deflated-GMRES
    solve of the local system with right-hand side R_j r, all subdomains and right-hand
-   sides in one launch.  r, z: device complex128 [nrhs][ndof], must not alias. */
+   sides in one launch (with coarse_intervals > 0 the two-level form, see dd_params).
+   r, z: device complex128 [nrhs][ndof], must not alias. */
 dd_status dd_apply_preconditioner(dd_handle* h, const void* r, void* z, void* stream);
 
 /* Solve A u = f by right-preconditioned FGMRES from u = 0 (Sec. 3).  f, u: device
@@ -198,6 +212,25 @@ dd_status dd_op_scatter(dd_handle* h, int precision, const void* u, void* z, voi
    iteration counts and flags (bit 0 guess accepted, bit 1 not converged). */
 dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void* u, int32_t* iters,
                             int32_t* flags, void* stream);
+
+/* ---- two-level method (coarse_intervals > 0) ---------------------------------------- */
+
+/* Coarse unknowns (M - 1)^2 of the global coarse space, 0 for the one-level method. */
+int64_t dd_global_coarse_size(const dd_handle* h);
+/* Host copy of E_0 = Z_0^T A Z_0 (real: A has Dirichlet conditions on the whole boundary
+   and Z_0 is real), 9 doubles per coarse unknown ((M-1)^2 of them, x fastest), neighbour
+   (cx+dx, cy+dy) at 3(dy+1) + (dx+1); and the smallest |pivot| met by the block
+   inversions of its cyclic reduction.  DD_EINVAL for a one-level handle. */
+dd_status dd_global_coarse_matrix(const dd_handle* h, double* out, double* min_pivot);
+/* t = Z_0^T r: global complex128 r [ndof] -> coarse complex128 t [(M-1)^2]; one
+   right-hand side. */
+dd_status dd_op_global_restrict(dd_handle* h, const void* r, void* t, void* stream);
+/* y = E_0^{-1} t by the FP64 block cyclic reduction; coarse complex128 vectors. */
+dd_status dd_op_global_coarse_solve(dd_handle* h, const void* t, void* y, void* stream);
+/* q = Z_0 y and w = r - A q: the coarse correction and the residual the subdomain
+   solves of the two-level preconditioner receive.  r, q, w global complex128 [ndof]
+   (q, w may be NULL to skip the copy out), y coarse. */
+dd_status dd_op_global_correct(dd_handle* h, const void* r, const void* y, void* q, void* w, void* stream);
 
 /* ---- learned initial guess ---------------------------------------------------------
  * The paper's subdomain GMRES starts from zero (Sec. 3).  A guess network maps the

@@ -49,6 +49,7 @@ class Params(ctypes.Structure):
         ("use_graph", ctypes.c_int),
         ("graph_steps", ctypes.c_int),
         ("local_solver", ctypes.c_int),
+        ("coarse_intervals", ctypes.c_int),
     ]
 
 
@@ -76,6 +77,8 @@ class Stats(ctypes.Structure):
         ("timed_steps", ctypes.c_int),
         ("ms_steps", ctypes.c_double),
         ("ms_guess", ctypes.c_double),
+        ("ms_coarse", ctypes.c_double),
+        ("coarse_bytes", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -153,6 +156,11 @@ _SIGS = {
     "dd_tile_descs": (ctypes.c_int, [_VP, ctypes.POINTER(TileDesc)]),
     "dd_outer_basis": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP]),
     "dd_last_inner": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _VP]),
+    "dd_global_coarse_size": (ctypes.c_int64, [_VP]),
+    "dd_global_coarse_matrix": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "dd_op_global_restrict": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "dd_op_global_coarse_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "dd_op_global_correct": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
 }
 
 
@@ -218,7 +226,7 @@ class Solver:
                  deflation: str = "linear", inner_precision: int = 64, inner_tol: float = 1e-2,
                  inner_maxit: int = 100, outer_tol: float = 1e-6, outer_maxit: int = 3000,
                  outer_restart: int = 0, nrhs: int = 1, use_graph: bool = True, graph_steps: int = 8,
-                 local_solver: str = "deflated"):
+                 local_solver: str = "deflated", coarse_intervals: int = 0):
         p = default_params()
         p.k, p.ppwl, p.n_intervals = k, ppwl, n_intervals
         p.px, p.py = px, py
@@ -241,6 +249,7 @@ class Solver:
         p.use_graph = 1 if use_graph else 0
         p.graph_steps = graph_steps
         p.local_solver = LOCAL_SOLVER[local_solver]
+        p.coarse_intervals = coarse_intervals
         self.params = p
         self._h = ctypes.c_void_p()
         torch = _torch()
@@ -254,6 +263,7 @@ class Solver:
         self.ncoarse = int(L.dd_packed_coarse_size(self._h))
         self.nrhs = nrhs
         self.inner_precision = inner_precision
+        self.nglobal_coarse = int(L.dd_global_coarse_size(self._h))
         lay = np.zeros(self.nsub * 12, dtype=np.int32)
         _check(L.dd_layout(self._h, lay.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "dd_layout")
         self.layout = lay.reshape(self.nsub, 12)
@@ -376,6 +386,35 @@ class Solver:
                                        flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        _stream(self.torch)), "dd_op_inner_solve")
         return u, iters, flags
+
+    # -- two-level method --
+    def global_coarse_matrix(self):
+        """E_0's coefficients ([(M-1)^2, 9] float64, neighbour (dx, dy) at 3(dy+1) + (dx+1)) and
+        the smallest |pivot| of its block cyclic reduction."""
+        out = np.zeros(self.nglobal_coarse * 9)
+        piv = ctypes.c_double()
+        _check(lib().dd_global_coarse_matrix(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             ctypes.byref(piv)), "dd_global_coarse_matrix")
+        return out.reshape(self.nglobal_coarse, 9), piv.value
+
+    def op_global_restrict(self, r):
+        t = self.torch.empty(self.nglobal_coarse, dtype=self.torch.complex128, device="cuda")
+        _check(lib().dd_op_global_restrict(self._h, _ptr(r), _ptr(t), _stream(self.torch)), "dd_op_global_restrict")
+        return t
+
+    def op_global_coarse_solve(self, t):
+        y = self.torch.empty_like(t)
+        _check(lib().dd_op_global_coarse_solve(self._h, _ptr(t), _ptr(y), _stream(self.torch)),
+               "dd_op_global_coarse_solve")
+        return y
+
+    def op_global_correct(self, r, y):
+        """(q, w) = (Z_0 y, r - A Z_0 y)."""
+        q = self.torch.empty_like(r)
+        w = self.torch.empty_like(r)
+        _check(lib().dd_op_global_correct(self._h, _ptr(r), _ptr(y), _ptr(q), _ptr(w), _stream(self.torch)),
+               "dd_op_global_correct")
+        return q, w
 
     # -- learned initial guess --
     def set_guess(self, net):

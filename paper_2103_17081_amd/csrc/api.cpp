@@ -12,6 +12,7 @@
 
 #include "ddhelm.h"
 #include "coarse.hpp"
+#include "gcoarse.hpp"
 #include "kernels.hpp"
 #include "net_host.hpp"
 #include "outer.hpp"
@@ -46,7 +47,7 @@ dd_status fail(dd_status s, const std::string& msg) {
 constexpr int kOuterBlocks = 1024;   // workgroups of the grid-stride outer kernels
 constexpr int kMaxRestart = 4000;    // Givens kernel stages a restart cycle in LDS
 constexpr int kMaxGraphSteps = 64;   // outer steps per captured graph
-constexpr int kEvPerStep = 7;        // phase events recorded per outer step
+constexpr int kEvPerStep = 8;        // phase events recorded per outer step
 
 }  // namespace
 
@@ -110,6 +111,8 @@ struct dd_handle {
   long long* foff = nullptr;    // [nsub] factor offsets
   std::vector<long long> foff_h;
   long long nffac = 0;
+  // two-level method (coarse_intervals > 0)
+  ddh::GlobalCoarse* gc = nullptr;
   std::vector<void*> allocs;
 
   template <typename T>
@@ -121,6 +124,8 @@ struct dd_handle {
     return DD_OK;
   }
   void release() {
+    delete gc;
+    gc = nullptr;
     for (void* q : allocs) (void)hipFree(q);
     allocs.clear();
     if (ev_ok)
@@ -194,6 +199,9 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   if (!(p->outer_tol > 0.0 && p->outer_tol < 1.0)) return fail(DD_EINVAL, "outer_tol must be in (0, 1)");
   if (p->outer_maxit < 1) return fail(DD_EINVAL, "outer_maxit must be >= 1");
   if (p->nrhs < 1 || p->nrhs > 64) return fail(DD_EINVAL, "nrhs must be in [1, 64]");
+  if (p->coarse_intervals != 0 &&
+      (p->coarse_intervals < 2 || p->coarse_intervals > n || p->coarse_intervals - 1 > ddh::kMaxGlobalCoarse))
+    return fail(DD_EINVAL, "coarse_intervals must be 0 (one-level) or in [2, N] with at most 513 intervals");
   if (p->use_graph && (p->graph_steps < 1 || p->graph_steps > kMaxGraphSteps))
     return fail(DD_EINVAL, "graph_steps must be in [1, 64]");
   auto cuts = [&](const int* c, int parts, std::vector<int>& out) -> dd_status {
@@ -377,11 +385,11 @@ ddh::DirectArgs direct_args(dd_handle* h) {
 
 dd_status run_inner(dd_handle* h, const cplx<double>* r, long long rstride, cplx<double>* z, long long zstride,
                     const int* done, hipStream_t st, const int* jdev = nullptr, long long rslot = 0,
-                    long long zslot = 0) {
+                    long long zslot = 0, const cplx<double>* zadd = nullptr) {
   if (h->direct) {
     auto a = direct_args(h);
     a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
-    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot; a.zadd = zadd;
     DD_HIP(ddh::launch_direct_solve(a, st));
     return DD_OK;
   }
@@ -390,21 +398,36 @@ dd_status run_inner(dd_handle* h, const cplx<double>* r, long long rstride, cplx
   if (h->prec == 32) {
     auto a = inner_args<float>(h);
     a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
-    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot; a.gtile = gt; a.gT = gT;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot; a.gtile = gt; a.gT = gT; a.zadd = zadd;
     DD_HIP(ddh::launch_inner_solve<float>(a, st));
   } else {
     auto a = inner_args<double>(h);
     a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
-    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot; a.gtile = gt; a.gT = gT;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot; a.gtile = gt; a.gT = gT; a.zadd = zadd;
     DD_HIP(ddh::launch_inner_solve<double>(a, st));
   }
   return DD_OK;
 }
 
+// Two-level coarse correction of the preconditioner input (no-op for the one-level
+// method): q = Z_0 E_0^{-1} Z_0^T r and w = r - A q into the handle's coarse workspace.
+dd_status run_coarse(dd_handle* h, const cplx<double>* r, long long rstride, const int* done, hipStream_t st,
+                     const int* jdev = nullptr, long long rslot = 0) {
+  if (!h->gc) return DD_OK;
+  DD_HIP(h->gc->restrict_rhs(r, rstride, jdev, rslot, done, h->nrhs, st));
+  DD_HIP(h->gc->solve(h->nrhs, st));
+  DD_HIP(h->gc->correct(r, rstride, jdev, rslot, done, h->nrhs, st));
+  return DD_OK;
+}
+
+// z = M^{-1} r: one-level (eq. 3), or two-level M_1^{-1} (r - A q) + q.
 dd_status run_apply(dd_handle* h, const cplx<double>* r, long long rstride, cplx<double>* z, long long zstride,
                     const int* done, hipStream_t st) {
-  DD_TRY(run_guess(h, r, rstride, done, st));
-  return run_inner(h, r, rstride, z, zstride, done, st);
+  DD_TRY(run_coarse(h, r, rstride, done, st));
+  const cplx<double>* rin = h->gc ? h->gc->w : r;
+  const long long rs = h->gc ? h->ndof : rstride;
+  DD_TRY(run_guess(h, rin, rs, done, st));
+  return run_inner(h, rin, rs, z, zstride, done, st, nullptr, 0, 0, h->gc ? h->gc->q : nullptr);
 }
 
 dd_status check_handle(const dd_handle* h) {
@@ -484,6 +507,13 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
         if (!(h->pivmin_h[j] > 0.0) || !std::isfinite(h->pivmin_h[j]))
           return fail(DD_ESINGULAR, "local matrix B_" + std::to_string(j) + " is singular (zero pivot)");
       DD_HIP(ddh::configure_direct(h->max_nj));
+    }
+    if (h->p.coarse_intervals > 0) {
+      h->gc = new ddh::GlobalCoarse();
+      const hipError_t e = h->gc->setup(h->n, h->p.coarse_intervals, h->p.k, h->nrhs, st);
+      if (e != hipSuccess) return fail(DD_EHIP, std::string("global coarse set-up: ") + hipGetErrorString(e));
+      if (!(h->gc->min_pivot > 0.0))
+        return fail(DD_ESINGULAR, "global coarse matrix E_0 has a zero (or non-finite) pivot in its block reduction");
     }
     if (h->prec == 32) DD_TRY(alloc_inner<float>(h));
     else DD_TRY(alloc_inner<double>(h));
@@ -607,21 +637,25 @@ static dd_status enqueue_outer_step(dd_handle* h, int slot, hipStream_t st, bool
     return DD_OK;
   };
   DD_TRY(mark(0));
-  DD_TRY(run_guess(h, h->Vo, vstr, o.done, st, h->jdev, nd));
+  DD_TRY(run_coarse(h, h->Vo, vstr, o.done, st, h->jdev, nd));
   DD_TRY(mark(1));
-  DD_TRY(run_inner(h, h->Vo, vstr, h->Zo, zstr, o.done, st, h->jdev, nd, nd));
+  if (h->gc) DD_TRY(run_guess(h, h->gc->w, nd, o.done, st));
+  else DD_TRY(run_guess(h, h->Vo, vstr, o.done, st, h->jdev, nd));
   DD_TRY(mark(2));
-  DD_HIP(ddh::launch_global_apply_masked(h->cs, h->Zo, zstr, h->Vo + nd, vstr, nr, o.done, st, sr, nd, nd));
+  if (h->gc) DD_TRY(run_inner(h, h->gc->w, nd, h->Zo, zstr, o.done, st, h->jdev, 0, nd, h->gc->q));
+  else DD_TRY(run_inner(h, h->Vo, vstr, h->Zo, zstr, o.done, st, h->jdev, nd, nd));
   DD_TRY(mark(3));
+  DD_HIP(ddh::launch_global_apply_masked(h->cs, h->Zo, zstr, h->Vo + nd, vstr, nr, o.done, st, sr, nd, nd));
+  DD_TRY(mark(4));
   DD_HIP(ddh::launch_dots2(h->Vo, vstr, nullptr, 0, nullptr, 0, nd, sr, 1, m, h->part, h->pstride, nr, o.done, st,
                            h->dots_blocks));
-  DD_TRY(mark(4));
+  DD_TRY(mark(5));
   DD_HIP(ddh::launch_reduce_parts(h->part, ddh::dots2_chunks(nd), h->pstride, sr, 2, 3, m, h->coef, h->pstride,
                                   nullptr, 0, 2, nr, o.done, st));
   DD_HIP(ddh::launch_dcgs2_step(o, sr, m, nd, h->coef, h->pstride, 1, h->ca, h->cb, m, h->scal, nr, st));
-  DD_TRY(mark(5));
-  DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, sr, h->ca, h->cb, m, h->scal, nr, o.done, st));
   DD_TRY(mark(6));
+  DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, sr, h->ca, h->cb, m, h->scal, nr, o.done, st));
+  DD_TRY(mark(7));
   DD_HIP(ddh::launch_advance_step(h->jdev, st));
   return DD_OK;
 }
@@ -662,7 +696,8 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
   DD_HIP(hipMemsetAsync(o.applies, 0, nr * sizeof(int), st));
   DD_HIP(hipMemsetAsync(o.sweep_bytes, 0, 2 * sizeof(unsigned long long), st));
   DD_HIP(hipMemsetAsync(u, 0, (size_t)nr * nd * sizeof(cplx<double>), st));
-  double ms[6] = {0, 0, 0, 0, 0, 0};   // guess, inner, global stencil, dot sweep, bookkeeping, update sweep
+  // coarse correction, guess, inner, global stencil, dot sweep, bookkeeping, update sweep
+  double ms[7] = {0, 0, 0, 0, 0, 0, 0};
   double ms_steps = 0.0;            // all outer steps (graph replays and eager steps)
   int launches = 0, replays = 0, timed_steps = 0;
   float el = 0.f;
@@ -713,7 +748,7 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
         timed_steps += batch;
         for (int q = 0; q < batch; ++q) {
           hipEvent_t* ev = h->sev.data() + (size_t)q * kEvPerStep;
-          for (int e = 0; e < 6; ++e) {
+          for (int e = 0; e < 7; ++e) {
             DD_HIP(hipEventElapsedTime(&el, ev[e], ev[e + 1]));
             ms[e] += el;
           }
@@ -761,13 +796,15 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
     stats->inner_iters_max = (int)c[2];
     stats->guesses_accepted = (long long)c[3];
     stats->inner_bytes = (double)c[4];
-    stats->ms_guess = ms[0];
-    stats->ms_inner = ms[1];
-    stats->ms_spmv = ms[2];
-    stats->ms_orth = ms[3] + ms[4] + ms[5];
-    stats->ms_other = ms[4];
-    stats->ms_dots = ms[3];
-    stats->ms_update = ms[5];
+    stats->ms_coarse = ms[0];
+    stats->coarse_bytes = h->gc ? (double)h->gc->solve_bytes() : 0.0;
+    stats->ms_guess = ms[1];
+    stats->ms_inner = ms[2];
+    stats->ms_spmv = ms[3];
+    stats->ms_orth = ms[4] + ms[5] + ms[6];
+    stats->ms_other = ms[5];
+    stats->ms_dots = ms[4];
+    stats->ms_update = ms[6];
     stats->dots_bytes = (double)sb[0];
     stats->update_bytes = (double)sb[1];
     stats->inner_launches = launches;
@@ -796,9 +833,10 @@ static std::string tune_signature(const dd_handle* h) {
   for (int c : h->cuts_x) mix(c);
   for (int c : h->cuts_y) mix(c + 1000003);
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "%s N=%d px=%d py=%d cuts=%016llx ov=%d bc=%d prec=%d maxit=%d nrhs=%d m=%d",
+  std::snprintf(buf, sizeof(buf),
+                "%s N=%d px=%d py=%d cuts=%016llx ov=%d bc=%d prec=%d maxit=%d nrhs=%d m=%d ls=%d M0=%d",
                 prop.gcnArchName, h->n, h->p.px, h->p.py, hc, h->p.overlap, h->p.local_bc, h->prec, h->maxit,
-                h->nrhs, h->restart);
+                h->nrhs, h->restart, h->p.local_solver, h->p.coarse_intervals);
   return buf;
 }
 
@@ -1116,6 +1154,54 @@ dd_status dd_outer_basis(dd_handle* h, int j, void* v, void* stream) {
   const long long nd = h->ndof, vstr = (long long)(h->restart + 1) * nd;
   DD_HIP(hipMemcpy2DAsync(v, nd * sizeof(cplx<double>), h->Vo + (long long)j * nd, vstr * sizeof(cplx<double>),
                           nd * sizeof(cplx<double>), h->nrhs, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return DD_OK;
+}
+
+// ---- two-level method ---------------------------------------------------------------
+
+int64_t dd_global_coarse_size(const dd_handle* h) { return (h && h->gc) ? h->gc->ncoarse : 0; }
+
+dd_status dd_global_coarse_matrix(const dd_handle* h, double* out, double* min_pivot) {
+  DD_TRY(check_handle(h));
+  if (!h->gc) return fail(DD_EINVAL, "the handle has no global coarse space (coarse_intervals = 0)");
+  if (!out) return fail(DD_EINVAL, "null argument");
+  DD_HIP(hipMemcpy(out, h->gc->E0c, (size_t)h->gc->ncoarse * 9 * sizeof(double), hipMemcpyDeviceToHost));
+  if (min_pivot) *min_pivot = h->gc->min_pivot;
+  return DD_OK;
+}
+
+dd_status dd_op_global_restrict(dd_handle* h, const void* r, void* t, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!h->gc) return fail(DD_EINVAL, "the handle has no global coarse space (coarse_intervals = 0)");
+  if (!r || !t) return fail(DD_EINVAL, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  DD_HIP(h->gc->restrict_rhs((const cplx<double>*)r, h->ndof, nullptr, 0, nullptr, 1, st));
+  DD_HIP(hipMemcpyAsync(t, h->gc->cv, (size_t)h->gc->ncoarse * sizeof(cplx<double>), hipMemcpyDeviceToDevice, st));
+  return DD_OK;
+}
+
+dd_status dd_op_global_coarse_solve(dd_handle* h, const void* t, void* y, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!h->gc) return fail(DD_EINVAL, "the handle has no global coarse space (coarse_intervals = 0)");
+  if (!t || !y) return fail(DD_EINVAL, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nb = (size_t)h->gc->ncoarse * sizeof(cplx<double>);
+  DD_HIP(hipMemcpyAsync(h->gc->cv, t, nb, hipMemcpyDeviceToDevice, st));
+  DD_HIP(h->gc->solve(1, st));
+  DD_HIP(hipMemcpyAsync(y, h->gc->cv + h->gc->ncoarse, nb, hipMemcpyDeviceToDevice, st));
+  return DD_OK;
+}
+
+dd_status dd_op_global_correct(dd_handle* h, const void* r, const void* y, void* q, void* w, void* stream) {
+  DD_TRY(check_handle(h));
+  if (!h->gc) return fail(DD_EINVAL, "the handle has no global coarse space (coarse_intervals = 0)");
+  if (!r || !y) return fail(DD_EINVAL, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nb = (size_t)h->gc->ncoarse * sizeof(cplx<double>), nf = (size_t)h->ndof * sizeof(cplx<double>);
+  DD_HIP(hipMemcpyAsync(h->gc->cv + h->gc->ncoarse, y, nb, hipMemcpyDeviceToDevice, st));
+  DD_HIP(h->gc->correct((const cplx<double>*)r, h->ndof, nullptr, 0, nullptr, 1, st));
+  if (q) DD_HIP(hipMemcpyAsync(q, h->gc->q, nf, hipMemcpyDeviceToDevice, st));
+  if (w) DD_HIP(hipMemcpyAsync(w, h->gc->w, nf, hipMemcpyDeviceToDevice, st));
   return DD_OK;
 }
 

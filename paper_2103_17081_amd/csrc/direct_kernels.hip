@@ -89,7 +89,10 @@ __global__ void __launch_bounds__(NT) direct_solve_kernel(DirectArgs a) {
     if (zout) {
       const int lj = n / nx, li = n - lj * nx;
       const int gi = d.i0 + li, gj = d.j0 + lj;
-      if (gi >= d.oi0 && gi <= d.oi1 && gj >= d.oj0 && gj <= d.oj1) zout[(long long)(gj - 1) * ldg + (gi - 1)] = x[n];
+      if (gi >= d.oi0 && gi <= d.oi1 && gj >= d.oj0 && gj <= d.oj1) {
+        const long long gidx = (long long)(gj - 1) * ldg + (gi - 1);
+        zout[gidx] = a.zadd ? x[n] + a.zadd[(long long)rhs * a.ndof + gidx] : x[n];
+      }
     }
   }
   if (tid == 0) {
@@ -100,7 +103,7 @@ __global__ void __launch_bounds__(NT) direct_solve_kernel(DirectArgs a) {
     atomicAdd(a.counters + 1, 1ull);
     const unsigned long long own = (unsigned long long)(d.oi1 - d.oi0 + 1) * (d.oj1 - d.oj0 + 1);
     const unsigned long long bytes =
-        16ull * (unsigned long long)coarse_factor_size(nx, ny) + 16ull * nj + 16ull * own;
+        16ull * (unsigned long long)coarse_factor_size(nx, ny) + 16ull * nj + (a.zadd ? 32ull : 16ull) * own;
     atomicAdd(a.counters + 4, bytes);
   }
 }

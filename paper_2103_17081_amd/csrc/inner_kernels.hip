@@ -513,8 +513,11 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
     if (a.U) a.U[fo + n] = ccast<T>(fnorm * ccast<double>(u));
     if (zout) {
       const int gi = d.i0 + li, gj = d.j0 + lj;
-      if (gi >= d.oi0 && gi <= d.oi1 && gj >= d.oj0 && gj <= d.oj1)
-        zout[(long long)rhs * a.zstride + (long long)(gj - 1) * ldg + (gi - 1)] = fnorm * ccast<double>(u);
+      if (gi >= d.oi0 && gi <= d.oi1 && gj >= d.oj0 && gj <= d.oj1) {
+        const long long gidx = (long long)(gj - 1) * ldg + (gi - 1);
+        const cplx<double> add = a.zadd ? a.zadd[(long long)rhs * a.ndof + gidx] : czero<double>();
+        zout[(long long)rhs * a.zstride + gidx] = fnorm * ccast<double>(u) + add;
+      }
     }
   }
   if (tid == 0) {
@@ -528,7 +531,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       const unsigned long long s = sizeof(cplx<T>), nn = (unsigned long long)nj, kk = (unsigned long long)k;
       const unsigned long long own = (unsigned long long)(d.oi1 - d.oi0 + 1) * (d.oj1 - d.oj0 + 1);
       const unsigned long long fac_bytes = 16ull * (unsigned long long)coarse_solve_values(d);
-      unsigned long long bytes = 16ull * nn + 16ull * own + (kk + 2) * fac_bytes +
+      unsigned long long bytes = 16ull * nn + (a.zadd ? 32ull : 16ull) * own + (kk + 2) * fac_bytes +
                                  s * nn * (2 * kk + 2 * kk * (kk + 1)) + 2 * s * nn;
       if (offered) bytes += fac_bytes + (a.gtile ? 8ull : s) * nn + 3 * s * nn;
       atomicAdd(a.counters + 4, bytes);

@@ -27,6 +27,7 @@ struct InnerArgs {
   const cplx<double>* Ec;        // coarse 9-point coefficients
   const cplx<double>* r;         // global right-hand sides [nrhs][ndof], or null: use F
   cplx<double>* z;               // global output [nrhs][ndof] (owned nodes), or null
+  const cplx<double>* zadd;      // added to z at the owned nodes ([nrhs][ndof], stride ndof), or null
   cplx<T>* F;                    // packed local right-hand sides
   cplx<T>* U;                    // packed local solutions, or null
   const cplx<T>* guess;          // packed initial guesses, or null
@@ -93,6 +94,7 @@ struct DirectArgs {
   const long long* foff;         // [nsub] factor offsets (complex<double> elements)
   const cplx<double>* r;         // global right-hand sides, or null: use F
   cplx<double>* z;               // global output (owned nodes), or null
+  const cplx<double>* zadd;      // added to z at the owned nodes ([nrhs][ndof], stride ndof), or null
   const cplx<double>* F;         // packed right-hand sides [nrhs][nfine]
   cplx<double>* U;               // packed solutions, or null
   const int* done;

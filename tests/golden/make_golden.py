@@ -3,13 +3,16 @@
 Usage: python tests/golden/make_golden.py small [medium] [large]
        python tests/golden/make_golden.py --spread small [medium]
        python tests/golden/make_golden.py --direct small [medium] [large]
+       python tests/golden/make_golden.py --two-level small:16 [medium:80]
 
 For each named workload (paper_2103_17081_amd.inputs.workload) and its first right-hand
 side, runs the oracle's outer FGMRES with impedance (ORAS) local matrices, linear
 deflation and deflated-GMRES subdomain solves at the workload's inner tolerance, and
 records the outer count, total inner iterations, subdomain solves and the true relative
 residual.  Existing entries for other workloads are kept.  --direct records, under
-"direct", the same run with exact (sparse LU) subdomain solves.
+"direct", the same run with exact (sparse LU) subdomain solves.  --two-level NAME:M
+records, under "two_level" -> "M", the oracle's two-level method (global coarse space of
+M coarse intervals per edge) with deflated-GMRES and with exact subdomain solves.
 """
 
 import json
@@ -100,9 +103,30 @@ def direct(names):
             json.dump(data, fh, indent=1, sort_keys=True)
 
 
+def two_level(specs):
+    from oracle import coarse_space
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for spec in specs:
+        name, m = spec.split(":")
+        w = inputs.workload(name)
+        T = coarse_space.TwoLevel(schwarz.Schwarz(schwarz.problem_from_workload(w)), int(m))
+        t = time.time()
+        _, st = T.solve(w.rhs[0], mode="deflated", inner_tol=w.inner_tol, outer_maxit=5000)
+        _, sd = T.solve(w.rhs[0], mode="direct", outer_maxit=5000)
+        data.setdefault(name, {}).setdefault("two_level", {})[m] = {
+            "outer_iters": st.outer_iters, "inner_iters": st.inner_iters, "subdomain_solves": st.subdomain_solves,
+            "true_relres": st.true_relres, "direct_outer_iters": sd.outer_iters,
+            "oracle_seconds": round(time.time() - t, 1)}
+        print(name, m, data[name]["two_level"][m], flush=True)
+        with open(OUT, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
-    if args and args[0] == "--direct":
+    if args and args[0] == "--two-level":
+        two_level(args[1:] or ["small:16"])
+    elif args and args[0] == "--direct":
         direct(args[1:] or ["small"])
     elif args and args[0] == "--spread":
         data = json.load(open(OUT)) if os.path.exists(OUT) else {}

@@ -26,7 +26,7 @@ def test_default_params():
     assert p.k == 20.0 and p.ppwl == 10.0 and p.px == 2 and p.py == 2
     assert p.overlap == 1 and p.local_bc == 0 and p.deflation == 0
     assert p.inner_precision == 64 and p.inner_tol == 1e-2 and p.outer_tol == 1e-6
-    assert p.nrhs == 1 and p.outer_restart == 0
+    assert p.nrhs == 1 and p.outer_restart == 0 and p.coarse_intervals == 0
 
 
 @pytest.mark.parametrize("kw,needle", [
@@ -43,6 +43,10 @@ def test_default_params():
     (dict(n_intervals=8, px=8, local_bc="dirichlet"), "2 x 2"),
     (dict(local_solver="direct", inner_precision=32), "direct local solves are FP64"),
     (dict(local_solver=5), "local_solver must be"),
+    (dict(n_intervals=32, coarse_intervals=1), "coarse_intervals"),
+    (dict(n_intervals=32, coarse_intervals=33), "coarse_intervals"),
+    (dict(n_intervals=1200, px=8, py=8, coarse_intervals=600), "coarse_intervals"),
+    (dict(coarse_intervals=-3), "coarse_intervals"),
 ])
 def test_invalid_parameters_rejected_on_host(kw, needle):
     st, msg = binding.setup_status(**kw)
@@ -58,6 +62,9 @@ def test_null_arguments():
     assert L.dd_apply_preconditioner(None, None, None, None) == binding.DD_EINVAL
     assert L.dd_solve(None, None, None, None, None) == binding.DD_EINVAL
     assert L.dd_layout(None, None) == binding.DD_EINVAL
+    assert L.dd_global_coarse_size(None) == 0
+    assert L.dd_global_coarse_matrix(None, None, None) == binding.DD_EINVAL
+    assert L.dd_op_global_restrict(None, None, None, None) == binding.DD_EINVAL
 
 
 def test_net_default_params():
