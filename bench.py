@@ -18,7 +18,9 @@ by one right after the timed solves (HIP cannot time events inside graph replays
 `roofline` is the one with the largest total time.  The CPU baseline is the oracle timed on a
 bounded sample of the same workload (its first outer iterations).  `direct_local_solves`
 times the same solve with exact subdomain solves (FP64 block LU of every local matrix, the
-direct-solve baseline of the paper's experiments) for comparison.
+direct-solve baseline of the paper's experiments) for comparison; `two_level` times the
+two-level method (a global coarse space added to the chosen form, the extension the
+paper proposes in its conclusions).
 """
 
 from __future__ import annotations
@@ -64,6 +66,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the all-FP64 comparison solve")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the comparison with exact (FP64 block-LU) subdomain solves")
+    ap.add_argument("--no-two-level", action="store_true",
+                    help="skip the two-level solve (global coarse space of --coarse-intervals per edge)")
+    ap.add_argument("--coarse-intervals", type=int, default=0,
+                    help="coarse intervals per edge of the two-level leg (0: N / 2, i.e. H = 2h)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-outer", type=int, default=40, help="outer iterations of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -71,11 +77,16 @@ def parse():
     return ap.parse_args()
 
 
-def make_solver(w, precision: int, local_solver: str = "deflated"):
+def make_solver(w, precision: int, local_solver: str = "deflated", coarse_intervals: int = 0):
     from paper_2103_17081_amd.binding import Solver
     return Solver(w.k, n_intervals=w.n, cuts_x=w.cuts_x, cuts_y=w.cuts_y, overlap=w.overlap,
                   inner_precision=precision, inner_tol=w.inner_tol, outer_tol=w.outer_tol,
-                  outer_maxit=4000, local_solver=local_solver)
+                  outer_maxit=4000, local_solver=local_solver, coarse_intervals=coarse_intervals)
+
+
+def default_coarse_intervals(w) -> int:
+    """M = N / 2: coarse spacing H = 2h, the coarsening of the subdomain deflation (Sec. 2)."""
+    return max(2, w.n // 2)
 
 
 def true_relres(torch, solver, f, u):
@@ -215,6 +226,43 @@ def main():
             "ms_per_precond_apply": di["ms_inner"] / max(di["precond_applies"], 1),
             "algorithmic_GB_per_apply": di["inner_bytes"] / max(di["precond_applies"], 1) / 1e9}
         direct.close()
+    if not args.no_two_level:
+        # the two-level method (global coarse space) the paper proposes as the next step
+        M = args.coarse_intervals or default_coarse_intervals(w)
+        t0 = time.perf_counter()
+        two = make_solver(w, 32, coarse_intervals=M)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        two.autotune(None)
+        t2, u2, s2 = timed_solves(torch, two, f, 1, 1)
+        two.set_graph(False)
+        _, ti = two.solve(f)
+        torch.cuda.synchronize()
+        ap2 = max(ti["precond_applies"], 1)
+        ms_c = ti["ms_coarse"] / ap2
+        ach = ti["coarse_bytes"] / (ms_c * 1e-3) / 1e9 if ms_c > 0 else 0.0
+        out["two_level"] = {
+            "coarse_intervals": M, "coarse_unknowns": two.nglobal_coarse, "setup_s": t_setup,
+            "time_to_solution_s": t2, "outer_iters": s2[-1]["outer_iters"],
+            "precond_applies": s2[-1]["precond_applies"],
+            "subdomain_solves_per_s": s2[-1]["subdomain_solves"] / t2,
+            "avg_inner_iters": s2[-1]["inner_iters_total"] / max(s2[-1]["subdomain_solves"], 1),
+            "true_relres": true_relres(torch, two, f, u2), "status": s2[-1]["status"],
+            "speedup_vs_one_level": (t / args.steps) / t2,
+            "coarse_correction": {"ms_per_apply": ms_c, "solve_bytes": ti["coarse_bytes"],
+                                  "achieved_GBs_vs_solve_bytes": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS},
+            "ms_phase_instrumented_solve": {"coarse": ti["ms_coarse"], "inner": ti["ms_inner"],
+                                            "spmv": ti["ms_spmv"], "orth": ti["ms_orth"],
+                                            "all_steps": ti["ms_steps"]}}
+        two.close()
+        # the same two-level method with exact (FP64 block-LU) subdomain solves
+        twod = make_solver(w, 64, "direct", coarse_intervals=M)
+        t3, u3, s3 = timed_solves(torch, twod, f, 1, 1)
+        out["two_level"]["with_direct_local_solves"] = {
+            "time_to_solution_s": t3, "outer_iters": s3[-1]["outer_iters"],
+            "true_relres": true_relres(torch, twod, f, u3), "status": s3[-1]["status"],
+            "speedup_vs_one_level": (t / args.steps) / t3}
+        twod.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_outer)
     print(json.dumps(out), flush=True)

@@ -52,7 +52,8 @@ __global__ void __launch_bounds__(256) gc_assemble_kernel(const int* __restrict_
 }
 
 // Dense level-0 blocks of block row i (coarse row i + 1): B_i (within the row),
-// A_i (to row i - 1), C_i (to row i + 1), at work + (3 i + {0, 1, 2}) n^2.
+// A_i (to row i - 1), C_i (to row i + 1), at work + (3 i + {0, 1, 2}) n^2, each stored
+// transposed: entry (r, c) at c n + r.
 __global__ void __launch_bounds__(256) gc_blocks_kernel(const double* __restrict__ E0c, int n,
                                                         double* __restrict__ work) {
   const long long nn = (long long)n * n;
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(256) gc_blocks_kernel(const double* __restrict
   const int i = (int)(e / (3 * nn));
   const long long rem = e - (long long)i * 3 * nn;
   const int which = (int)(rem / nn);
-  const int r = (int)((rem % nn) / n), c = (int)(rem % n);
+  const int c = (int)((rem % nn) / n), r = (int)(rem % n);
   const int dx = c - r, dy = which == 0 ? 0 : (which == 1 ? -1 : 1);
   double v = 0.0;
   if (dx >= -1 && dx <= 1) v = E0c[((long long)i * n + r) * 9 + 3 * (dy + 1) + (dx + 1)];
@@ -211,53 +212,130 @@ __global__ void __launch_bounds__(kInvThreads) gc_inverse_kernel(const InvTask* 
   if (tid == 0) pivmin[blockIdx.x] = minp;
 }
 
-// One level of the block cyclic reduction solve: for task blockIdx.y and rows
-// [blockIdx.x * 4 rpw, +4 rpw) of its output block,
+// One level of the block cyclic reduction solve: for task blockIdx.y and output rows
+// [blockIdx.x * RPB, +RPB) of its block,
 //   out = (base ? out : 0) + sum_t mat_t in_t,
-// one wave per row (lanes stride over the columns), all right-hand sides per matrix
-// read, in groups of kBcrRhsGroup.
-__global__ void __launch_bounds__(256) gc_bcr_kernel(const BcrTask* __restrict__ tasks, int first,
-                                                     const double* __restrict__ fac, cplx<double>* cv,
-                                                     long long cvstride, int n, int nrhs, int rpw) {
+// with the matrices stored transposed, so lane r of each of the 256 / RPB column slices
+// reads entries (k, row0 + r) of consecutive rows: coalesced, one output row per lane,
+// the slices summed through LDS at the end.  Every matrix entry is read once for all
+// right-hand sides of a group of kBcrRhsGroup.
+template <int RPB, int NT>
+__global__ void __launch_bounds__(NT) gc_bcr_kernel(const BcrTask* __restrict__ tasks, int first,
+                                                    const double* __restrict__ fac, cplx<double>* cv,
+                                                    long long cvstride, int n, int nrhs) {
+  constexpr int S = NT / RPB;
   const BcrTask t = tasks[first + blockIdx.y];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int rbase = (blockIdx.x * 4 + wave) * rpw;
-  for (int rr = 0; rr < rpw; ++rr) {
-    const int row = rbase + rr;
-    if (row >= n) break;
-    for (int g = 0; g < nrhs; g += kBcrRhsGroup) {
-      const int ng = min(kBcrRhsGroup, nrhs - g);
-      double are[kBcrRhsGroup], aim[kBcrRhsGroup];
+  const int r = threadIdx.x % RPB, sl = threadIdx.x / RPB;
+  const int row = blockIdx.x * RPB + r;
+  const bool live = row < n;
+  __shared__ double red[2][NT];
+  for (int g = 0; g < nrhs; g += kBcrRhsGroup) {
+    const int ng = min(kBcrRhsGroup, nrhs - g);
+    double are[kBcrRhsGroup], aim[kBcrRhsGroup];
 #pragma unroll
-      for (int s = 0; s < kBcrRhsGroup; ++s) { are[s] = 0.0; aim[s] = 0.0; }
-      for (int term = 0; term < t.nt; ++term) {
-        const double* __restrict__ m = fac + t.mat[term] + (long long)row * n;
-        const cplx<double>* __restrict__ v = cv + (long long)g * cvstride + t.in[term];
-        for (int c = lane; c < n; c += kWave) {
-          const double a = m[c];
+    for (int q = 0; q < kBcrRhsGroup; ++q) { are[q] = 0.0; aim[q] = 0.0; }
+    if (live) {
+      // tiled blocks: entry (row, k) at tile (row / kBcrTile), k kBcrTile + row % kBcrTile
+      const long long roff = (long long)(row / kBcrTile) * n * kBcrTile + row % kBcrTile;
+      // chunks of CH columns per lane for all terms at once, every load in flight
+      // together (indices past the end are clamped and their entries zeroed, so every
+      // load stays in bounds)
+      constexpr int CH = 8;
+      for (int k0 = sl; k0 < n; k0 += CH * S) {
+        double mk[3][CH];
 #pragma unroll
-          for (int s = 0; s < kBcrRhsGroup; ++s) {
-            if (s < ng) {
-              const cplx<double> x = v[(long long)s * cvstride + c];
-              are[s] = fma(a, x.re, are[s]);
-              aim[s] = fma(a, x.im, aim[s]);
+        for (int tm = 0; tm < 3; ++tm) {
+          if (tm < t.nt) {
+            const double* __restrict__ m = fac + t.mat[tm] + roff;
+#pragma unroll
+            for (int u = 0; u < CH; ++u) mk[tm][u] = m[(long long)min(k0 + u * S, n - 1) * kBcrTile];
+          }
+        }
+#pragma unroll
+        for (int tm = 0; tm < 3; ++tm)
+#pragma unroll
+          for (int u = 0; u < CH; ++u)
+            if (tm >= t.nt || k0 + u * S >= n) mk[tm][u] = 0.0;
+#pragma unroll
+        for (int q = 0; q < kBcrRhsGroup; ++q) {
+          if (q < ng) {
+#pragma unroll
+            for (int tm = 0; tm < 3; ++tm) {
+              if (tm < t.nt) {
+                const cplx<double>* __restrict__ v = cv + (long long)(g + q) * cvstride + t.in[tm];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                  const cplx<double> x = v[min(k0 + u * S, n - 1)];
+                  are[q] = fma(mk[tm][u], x.re, are[q]);
+                  aim[q] = fma(mk[tm][u], x.im, aim[q]);
+                }
+              }
             }
           }
         }
       }
+    }
+    // sum the S column slices of each right-hand side through LDS
 #pragma unroll
-      for (int s = 0; s < kBcrRhsGroup; ++s) {
-        if (s < ng) {
-          const double re = wave_sum(are[s]), im = wave_sum(aim[s]);
-          if (lane == 0) {
-            cplx<double>* o = cv + (long long)(g + s) * cvstride + t.out + row;
-            const cplx<double> prev = t.base ? *o : czero<double>();
-            *o = cplx<double>{prev.re + re, prev.im + im};
+    for (int q = 0; q < kBcrRhsGroup; ++q) {
+      if (q < ng) {
+        red[0][threadIdx.x] = are[q];
+        red[1][threadIdx.x] = aim[q];
+        __syncthreads();
+        if (sl == 0 && live) {
+          double re = 0.0, im = 0.0;
+          for (int j = 0; j < S; ++j) {
+            re += red[0][j * RPB + r];
+            im += red[1][j * RPB + r];
           }
+          cplx<double>* o = cv + (long long)(g + q) * cvstride + t.out + row;
+          const cplx<double> prev = t.base ? *o : czero<double>();
+          *o = cplx<double>{prev.re + re, prev.im + im};
         }
+        __syncthreads();
       }
     }
   }
+}
+
+// Solve layout of the factors: block b (n x n, stored transposed, b nn + k n + row) to
+// kBcrTile-row tiles, b tsz + (row / kBcrTile) n kBcrTile + k kBcrTile + row % kBcrTile,
+// so that a workgroup of the solve streams its rows' tile contiguously.
+__global__ void __launch_bounds__(256) gc_tile_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                      int n, long long nblocks, long long tsz) {
+  const long long nn = (long long)n * n;
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= nblocks * nn) return;
+  const long long b = e / nn;
+  const int k = (int)((e % nn) / n), row = (int)(e % n);
+  dst[b * tsz + (long long)(row / kBcrTile) * n * kBcrTile + (long long)k * kBcrTile + row % kBcrTile] = src[e];
+}
+
+// Level-0 couplings applied directly from the coarse operator's rows:
+//   out -= A_row in0 + C_row in1,
+// A_row / C_row the tridiagonal couplings of block row `row` to the rows below / above
+// (E_0 coefficients with dy = -1 / +1).  One thread per entry, grid z over right-hand sides.
+__global__ void __launch_bounds__(256) gc_sparse_kernel(const SpTask* __restrict__ tasks, int first,
+                                                        const double* __restrict__ E0c, cplx<double>* cv,
+                                                        long long cvstride, int n) {
+  const SpTask t = tasks[first + blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  cplx<double>* base = cv + (long long)blockIdx.z * cvstride;
+  cplx<double> acc = base[t.out + j];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    if (!t.has[side]) continue;
+    const double* cf = E0c + ((long long)t.row * n + j) * 9 + (side ? 6 : 0);
+    const cplx<double>* v = base + t.in[side];
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int jj = j + dx;
+      if (jj < 0 || jj >= n) continue;
+      acc = acc - cf[dx + 1] * v[jj];
+    }
+  }
+  base[t.out + j] = acc;
 }
 
 // b = Z_0^T r: one thread per coarse unknown, summing its hat's support.
@@ -408,22 +486,32 @@ hipError_t GlobalCoarse::setup(int n, int m, double k, int nr, hipStream_t st) {
   GC_TRY(alloc(&w, (size_t)nr * ndof));
 
   // ---- plan the block cyclic reduction ----
+  // Work blocks: B_i, A_i, C_i per block row, then the level-0 products Fm_i, Fp_i that
+  // only the set-up needs.
   auto Bw = [&](int i) { return 3LL * i * nn; };
   auto Aw = [&](int i) { return (3LL * i + 1) * nn; };
   auto Cw = [&](int i) { return (3LL * i + 2) * nn; };
   auto bvec = [&](int i) { return i * bn; };
   auto xvec = [&](int i) { return (int)(ncoarse + (long long)i * bn); };
-  long long nf = 0;
+  long long nf = 0, nw = 3LL * nb * nn;
   auto newfac = [&]() { const long long o = nf; nf += nn; return o; };
+  auto newwork = [&]() { const long long o = nw; nw += nn; return o; };
+  // Every block is stored transposed (column-major), which lets the solve kernel give
+  // each lane an output row with coalesced loads and no cross-lane reduction; a product
+  // X Y of true blocks is then the stored product Y^T X^T.
+  auto mul = [](std::vector<GemmTask>& v, long long x, int xa, long long y, int ya, long long c, int ca, int acc,
+                double sign) { v.push_back(GemmTask{{y, x, c}, {ya, xa, ca}, acc, sign}); };
   std::vector<LevelPlan> plans;
-  std::vector<std::vector<BcrTask>> red, back;
-  std::vector<BcrTask> top;
+  // solve launches: dense (BcrTask) or sparse (SpTask) phases, reductions upward
+  std::vector<std::pair<int, std::vector<BcrTask>>> red_dense, back_dense;   // (level, tasks)
+  std::vector<SpTask> red0_sparse, back0_sparse;
+  std::vector<BcrTask> red0_dense, back0_dense, top;
   std::vector<int> act(nb);
   for (int i = 0; i < nb; ++i) act[i] = i;
   std::vector<char> hasA(nb), hasC(nb);
   for (int i = 0; i < nb; ++i) { hasA[i] = i > 0; hasC[i] = i < nb - 1; }
   std::vector<long long> binv(nb, -1);
-  while (true) {
+  for (int level = 0;; ++level) {
     const int cnt = (int)act.size();
     LevelPlan lp;
     if (cnt == 1) {
@@ -436,6 +524,11 @@ hipError_t GlobalCoarse::setup(int n, int m, double k, int nr, hipStream_t st) {
       top.push_back(tk);
       break;
     }
+    // On level 0 the couplings A_i, C_i are the coarse operator's tridiagonal rows, so the
+    // solve applies them directly (sparse phases) and keeps only Binv_e: the reduction
+    // forms y_e = Binv_e b_e (into x_e, as scratch) and b_i -= A_i y_{i-1} + C_i y_{i+1};
+    // the back substitution forms b_e -= A_e x_{e-1} + C_e x_{e+1} and x_e = Binv_e b_e.
+    const bool sparse = level == 0;
     std::vector<BcrTask> rl, bl;
     for (int p = 1; p < cnt; p += 2) {
       const int e = act[p];
@@ -444,75 +537,117 @@ hipError_t GlobalCoarse::setup(int n, int m, double k, int nr, hipStream_t st) {
       BcrTask tk{};
       tk.out = xvec(e); tk.base = 0;
       tk.mat[0] = binv[e]; tk.in[0] = bvec(e); tk.nt = 1;
+      if (sparse) {
+        red0_dense.push_back(tk);
+        back0_dense.push_back(tk);
+        SpTask sk{};
+        sk.out = bvec(e); sk.row = e;
+        sk.in[0] = xvec(act[p - 1]); sk.has[0] = 1;
+        if (p + 1 < cnt) { sk.in[1] = xvec(act[p + 1]); sk.has[1] = 1; }
+        back0_sparse.push_back(sk);
+        continue;
+      }
       const long long P = newfac();
-      lp.g1.push_back(GemmTask{{binv[e], Aw(e), P}, {0, 1, 0}, 0, -1.0});
+      mul(lp.g1, binv[e], 0, Aw(e), 1, P, 0, 0, -1.0);
       tk.mat[tk.nt] = P; tk.in[tk.nt] = xvec(act[p - 1]); tk.nt++;
       if (p + 1 < cnt) {
         const long long R = newfac();
-        lp.g1.push_back(GemmTask{{binv[e], Cw(e), R}, {0, 1, 0}, 0, -1.0});
+        mul(lp.g1, binv[e], 0, Cw(e), 1, R, 0, 0, -1.0);
         tk.mat[tk.nt] = R; tk.in[tk.nt] = xvec(act[p + 1]); tk.nt++;
       }
       bl.push_back(tk);
     }
     std::vector<int> kept;
     std::vector<char> nA, nC;
+    const int fa = sparse ? 1 : 0;   // Fm, Fp: set-up work blocks on level 0, factors above
     for (int p = 0; p < cnt; p += 2) {
       const int i = act[p];
       BcrTask tk{};
       tk.out = bvec(i); tk.base = 1; tk.nt = 0;
+      SpTask sk{};
+      sk.out = bvec(i); sk.row = i;
       bool newA = false, newC = false;
       if (p >= 1) {
         const int em = act[p - 1];
-        const long long Fm = newfac();
-        lp.g1.push_back(GemmTask{{Aw(i), binv[em], Fm}, {1, 0, 0}, 0, -1.0});
-        lp.g2.push_back(GemmTask{{Fm, Cw(em), Bw(i)}, {0, 1, 1}, 1, 1.0});
+        const long long Fm = sparse ? newwork() : newfac();
+        mul(lp.g1, Aw(i), 1, binv[em], 0, Fm, fa, 0, -1.0);
+        mul(lp.g2, Fm, fa, Cw(em), 1, Bw(i), 1, 1, 1.0);
         if (hasA[em]) {
-          lp.g2.push_back(GemmTask{{Fm, Aw(em), Aw(i)}, {0, 1, 1}, 0, 1.0});
+          mul(lp.g2, Fm, fa, Aw(em), 1, Aw(i), 1, 0, 1.0);
           newA = true;
         }
         tk.mat[tk.nt] = Fm; tk.in[tk.nt] = bvec(em); tk.nt++;
+        sk.in[0] = xvec(em); sk.has[0] = 1;
       }
       if (p + 1 < cnt) {
         const int ep = act[p + 1];
-        const long long Fp = newfac();
-        lp.g1.push_back(GemmTask{{Cw(i), binv[ep], Fp}, {1, 0, 0}, 0, -1.0});
-        lp.g3.push_back(GemmTask{{Fp, Aw(ep), Bw(i)}, {0, 1, 1}, 1, 1.0});
+        const long long Fp = sparse ? newwork() : newfac();
+        mul(lp.g1, Cw(i), 1, binv[ep], 0, Fp, fa, 0, -1.0);
+        mul(lp.g3, Fp, fa, Aw(ep), 1, Bw(i), 1, 1, 1.0);
         if (hasC[ep]) {
-          lp.g2.push_back(GemmTask{{Fp, Cw(ep), Cw(i)}, {0, 1, 1}, 0, 1.0});
+          mul(lp.g2, Fp, fa, Cw(ep), 1, Cw(i), 1, 0, 1.0);
           newC = true;
         }
         tk.mat[tk.nt] = Fp; tk.in[tk.nt] = bvec(ep); tk.nt++;
+        sk.in[1] = xvec(ep); sk.has[1] = 1;
       }
-      if (tk.nt) rl.push_back(tk);
+      if (sparse) {
+        if (sk.has[0] || sk.has[1]) red0_sparse.push_back(sk);
+      } else if (tk.nt) {
+        rl.push_back(tk);
+      }
       kept.push_back(i);
       nA.push_back(newA);
       nC.push_back(newC);
     }
     for (size_t t = 0; t < kept.size(); ++t) { hasA[kept[t]] = nA[t]; hasC[kept[t]] = nC[t]; }
     plans.push_back(lp);
-    red.push_back(rl);
-    back.push_back(bl);
+    if (!sparse) {
+      red_dense.emplace_back(level, rl);
+      back_dense.emplace_back(level, bl);
+    }
     act = kept;
   }
   nfac = nf;
-  // solve phases: reductions upward, the top, back substitutions downward
+  // solve phases in order: level-0 reduction (dense, sparse), higher reductions, the top,
+  // higher back substitutions downward, level-0 back substitution (sparse, dense)
   std::vector<BcrTask> all;
+  std::vector<SpTask> all_sp;
   phases.clear();
-  auto add_phase = [&](const std::vector<BcrTask>& v) {
+  auto add_dense = [&](const std::vector<BcrTask>& v) {
     if (v.empty()) return;
-    phases.push_back(BcrPhase{(int)all.size(), (int)v.size()});
+    phases.push_back(BcrPhase{(int)all.size(), (int)v.size(), 0});
     all.insert(all.end(), v.begin(), v.end());
   };
-  for (auto& v : red) add_phase(v);
-  add_phase(top);
-  for (int l = (int)back.size() - 1; l >= 0; --l) add_phase(back[l]);
+  auto add_sparse = [&](const std::vector<SpTask>& v) {
+    if (v.empty()) return;
+    phases.push_back(BcrPhase{(int)all_sp.size(), (int)v.size(), 1});
+    all_sp.insert(all_sp.end(), v.begin(), v.end());
+  };
+  add_dense(red0_dense);
+  add_sparse(red0_sparse);
+  for (auto& v : red_dense) add_dense(v.second);
+  add_dense(top);
+  for (int l = (int)back_dense.size() - 1; l >= 0; --l) add_dense(back_dense[l].second);
+  add_sparse(back0_sparse);
+  add_dense(back0_dense);
   solve_bytes_ = 0;
   for (const BcrTask& tk : all) solve_bytes_ += (long long)tk.nt * nn * 8 + (long long)(tk.nt + 1 + tk.base) * bn * 16;
+  for (const SpTask& sk : all_sp)
+    solve_bytes_ += (long long)(sk.has[0] + sk.has[1]) * bn * (3 * 8 + 16) + 2LL * bn * 16;
 
   // ---- factor on the device ----
-  GC_TRY(alloc(&fac, (size_t)nfac));
+  // The set-up works on plain n x n blocks (sfac); the solve reads them re-laid in row
+  // tiles (fac): block b moves from offset b nn to b tsz.
+  const long long nblk = nfac / nn, tsz = (long long)((bn + kBcrTile - 1) / kBcrTile) * kBcrTile * bn;
+  for (BcrTask& tk : all)
+    for (int q = 0; q < tk.nt; ++q) tk.mat[q] = (tk.mat[q] / nn) * tsz;
+  GC_TRY(alloc(&fac, (size_t)(nblk * tsz)));
   GC_TRY(alloc(&tasks, all.size()));
   GC_TRY(hipMemcpyAsync(tasks, all.data(), sizeof(BcrTask) * all.size(), hipMemcpyHostToDevice, st));
+  GC_TRY(alloc(&sptasks, std::max<size_t>(all_sp.size(), 1)));
+  if (!all_sp.empty())
+    GC_TRY(hipMemcpyAsync(sptasks, all_sp.data(), sizeof(SpTask) * all_sp.size(), hipMemcpyHostToDevice, st));
   size_t ninv = 0, ngemm = 0, maxg = 0, maxi = 0;
   for (auto& lp : plans) {
     ninv += lp.inv.size();
@@ -524,7 +659,9 @@ hipError_t GlobalCoarse::setup(int n, int m, double k, int nr, hipStream_t st) {
   InvTask* dinv = nullptr;
   GemmTask* dgemm = nullptr;
   double* dpiv = nullptr;
-  hipError_t err = hipMalloc(&work, sizeof(double) * (size_t)(3 * nb) * nn);
+  double* sfac = nullptr;
+  hipError_t err = hipMalloc(&work, sizeof(double) * (size_t)nw);
+  if (err == hipSuccess) err = hipMalloc(&sfac, sizeof(double) * (size_t)nfac);
   if (err == hipSuccess) err = hipMalloc(&dinv, sizeof(InvTask) * std::max<size_t>(ninv, 1));
   if (err == hipSuccess) err = hipMalloc(&dgemm, sizeof(GemmTask) * std::max<size_t>(ngemm, 1));
   if (err == hipSuccess) err = hipMalloc(&dpiv, sizeof(double) * std::max<size_t>(ninv, 1));
@@ -551,20 +688,27 @@ hipError_t GlobalCoarse::setup(int n, int m, double k, int nr, hipStream_t st) {
   for (auto& lp : plans) {
     if (err != hipSuccess) break;
     hipLaunchKernelGGL(gc_inverse_kernel, dim3((unsigned)lp.inv.size()), dim3(kInvThreads), 0, st, dinv + io,
-                       (const double*)work, fac, bn, dpiv + io);
+                       (const double*)work, sfac, bn, dpiv + io);
     err = hipGetLastError();
     io += lp.inv.size();
     for (const auto* g : {&lp.g1, &lp.g2, &lp.g3}) {
       if (err != hipSuccess || g->empty()) continue;
       hipLaunchKernelGGL(gc_gemm_kernel, dim3((unsigned)(tiles * tiles), (unsigned)g->size()), dim3(256), 0, st,
-                         dgemm + go, fac, work, bn);
+                         dgemm + go, sfac, work, bn);
       err = hipGetLastError();
       go += g->size();
     }
   }
+  if (err == hipSuccess) {
+    const long long tot = nblk * nn;
+    hipLaunchKernelGGL(gc_tile_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, (const double*)sfac, fac,
+                       bn, nblk, tsz);
+    err = hipGetLastError();
+  }
   std::vector<double> piv(ninv, 0.0);
   if (err == hipSuccess) err = hipMemcpyAsync(piv.data(), dpiv, sizeof(double) * ninv, hipMemcpyDeviceToHost, st);
   if (err == hipSuccess) err = hipStreamSynchronize(st);
+  (void)hipFree(sfac);
   (void)hipFree(work);
   (void)hipFree(dinv);
   (void)hipFree(dgemm);
@@ -591,12 +735,26 @@ hipError_t GlobalCoarse::restrict_rhs(const cplx<double>* r, long long rstride, 
 
 hipError_t GlobalCoarse::solve(int nr, hipStream_t st) {
   for (const BcrPhase& ph : phases) {
-    // rows per wave: spread small levels over more workgroups
-    int rpw = 4;
-    while (rpw > 1 && (long long)ph.count * ((nc + 4 * rpw - 1) / (4 * rpw)) < 1024) rpw /= 2;
-    const unsigned gx = (unsigned)((nc + 4 * rpw - 1) / (4 * rpw));
-    hipLaunchKernelGGL(gc_bcr_kernel, dim3(gx, (unsigned)ph.count), dim3(256), 0, st, (const BcrTask*)tasks,
-                       ph.first, (const double*)fac, cv, 2 * ncoarse, nc, nr, rpw);
+    if (ph.kind == 1) {
+      hipLaunchKernelGGL(gc_sparse_kernel, dim3((unsigned)((nc + 255) / 256), (unsigned)ph.count, (unsigned)nr),
+                         dim3(256), 0, st, (const SpTask*)sptasks, ph.first, (const double*)E0c, cv, 2 * ncoarse, nc);
+      GC_TRY(hipGetLastError());
+      continue;
+    }
+    // Rows per workgroup (measured on the k = 200, N = 637, M = 318 solve): 64 (4 column
+    // slices) when the level has many tasks, 16 (16 slices) down to 8 tasks, 4 (64
+    // slices) on the last levels, where the launch is bound by load latency.
+    const long long c = ph.count;
+    if (c * ((nc + 63) / 64) >= 384) {
+      hipLaunchKernelGGL((gc_bcr_kernel<64, 256>), dim3((unsigned)((nc + 63) / 64), (unsigned)c), dim3(256), 0, st,
+                         (const BcrTask*)tasks, ph.first, (const double*)fac, cv, 2 * ncoarse, nc, nr);
+    } else if (c >= 8) {
+      hipLaunchKernelGGL((gc_bcr_kernel<16, 256>), dim3((unsigned)((nc + 15) / 16), (unsigned)c), dim3(256), 0, st,
+                         (const BcrTask*)tasks, ph.first, (const double*)fac, cv, 2 * ncoarse, nc, nr);
+    } else {
+      hipLaunchKernelGGL((gc_bcr_kernel<4, 256>), dim3((unsigned)((nc + 3) / 4), (unsigned)c), dim3(256), 0, st,
+                         (const BcrTask*)tasks, ph.first, (const double*)fac, cv, 2 * ncoarse, nc, nr);
+    }
     GC_TRY(hipGetLastError());
   }
   return hipSuccess;

@@ -23,7 +23,8 @@
 //   reduction, level by level:   b_i += Fm_i b_{i-1} + Fp_i b_{i+1}
 //   top:                         x_r = Binv_r b_r
 //   back substitution, downward: x_e = Binv_e b_e + P_e x_{e-1} + R_e x_{e+1}
-// (neighbours taken within the level).  Every step of a level is a set of
+// (neighbours taken within the level).  On level 0 the couplings are the tridiagonal
+// rows of E_0, so there the solve applies them directly and reads only Binv_e.  Every step of a level is a set of
 // independent dense n x n matrix-vector products, spread over the whole chip, so the
 // solve has 2 ceil(log2 nb) + 1 dependent launches instead of the 2 nb serial block
 // steps of a block LU.  The set-up computes the dense blocks with a batched FP64
@@ -39,10 +40,11 @@ namespace ddh {
 
 constexpr int kMaxGlobalCoarse = 512;   // largest coarse block n = M - 1
 constexpr int kBcrRhsGroup = 8;         // right-hand sides per pass of the solve kernel
+constexpr int kBcrTile = 64;            // rows per tile of the factors' solve layout
 
 // One dense block product of the solve: out = (base ? out : 0) + sum_t mat_t * in_t.
-// Offsets are elements of the factor array (matrices, n x n row-major) and of one
-// right-hand side's coarse vector segment [b (nb n) | x (nb n)].
+// Offsets are elements of the factor array (n x n matrices stored transposed, i.e.
+// column-major) and of one right-hand side's coarse vector segment [b (nb n) | x (nb n)].
 struct BcrTask {
   long long mat[3];
   int in[3];
@@ -66,8 +68,17 @@ struct InvTask {
   long long src, dst;
 };
 
+// Level-0 coupling update of the solve: out -= A_row in[0] + C_row in[1] (offsets in one
+// right-hand side's coarse vector segment; has[s] = 0 drops a side).
+struct SpTask {
+  int out, row;
+  int in[2];
+  int has[2];
+};
+
 struct BcrPhase {
-  int first, count;   // tasks [first, first + count) of the solve task table
+  int first, count;   // tasks [first, first + count) of the dense or sparse task table
+  int kind;           // 0 dense block products (BcrTask), 1 level-0 couplings (SpTask)
 };
 
 class GlobalCoarse {
@@ -87,6 +98,7 @@ class GlobalCoarse {
   double* E0c = nullptr;         // [ncoarse][9] coefficients, neighbour (dx, dy) at 3 (dy + 1) + (dx + 1)
   double* fac = nullptr;         // block cyclic reduction factors (real: A and Z_0 are real)
   BcrTask* tasks = nullptr;
+  SpTask* sptasks = nullptr;
   cplx<double>* cv = nullptr;    // [nrhs][2 ncoarse] coarse vectors b | x
   cplx<double>* q = nullptr;     // [nrhs][ndof] coarse correction Z_0 x
   cplx<double>* w = nullptr;     // [nrhs][ndof] corrected residual r - A q

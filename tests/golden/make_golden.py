@@ -103,6 +103,25 @@ def direct(names):
             json.dump(data, fh, indent=1, sort_keys=True)
 
 
+def perturbed_two_level(T, w, seeds=4, eps=1e-12):
+    """Outer counts of the oracle's two-level method when every coarse solution is
+    multiplied by (1 + eps xi), xi standard normal (seeded): the spread that coarse solves
+    accurate to ~1e-12 relative, instead of the sparse LU's ~1e-16, can cause."""
+    import numpy as np
+    exact = T.coarse.coarse_solve
+    out = {}
+    for mode in ("deflated", "direct"):
+        counts = []
+        for sd in range(seeds):
+            rng = np.random.default_rng(2000 + sd)
+            T.coarse.coarse_solve = lambda t, r=rng: (lambda y: y * (1 + eps * r.standard_normal(y.size)))(exact(t))
+            _, st = T.solve(w.rhs[0], mode=mode, inner_tol=w.inner_tol, outer_maxit=5000)
+            counts.append(st.outer_iters)
+        out[mode] = counts
+    T.coarse.coarse_solve = exact
+    return out
+
+
 def two_level(specs):
     from oracle import coarse_space
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
@@ -113,10 +132,13 @@ def two_level(specs):
         t = time.time()
         _, st = T.solve(w.rhs[0], mode="deflated", inner_tol=w.inner_tol, outer_maxit=5000)
         _, sd = T.solve(w.rhs[0], mode="direct", outer_maxit=5000)
-        data.setdefault(name, {}).setdefault("two_level", {})[m] = {
+        entry = {
             "outer_iters": st.outer_iters, "inner_iters": st.inner_iters, "subdomain_solves": st.subdomain_solves,
             "true_relres": st.true_relres, "direct_outer_iters": sd.outer_iters,
             "oracle_seconds": round(time.time() - t, 1)}
+        if name == "small":
+            entry["coarse_perturbed_outer"] = perturbed_two_level(T, w)
+        data.setdefault(name, {}).setdefault("two_level", {})[m] = entry
         print(name, m, data[name]["two_level"][m], flush=True)
         with open(OUT, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)

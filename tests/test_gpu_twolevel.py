@@ -10,11 +10,18 @@ Tolerances:
   times cond(E_0) eps; on these grids that is below 1e-6 (the worst case measured with
   the same reduction in numpy is 6e-8, k=200, N=637, M=106), and the GPU residual
   ||E_0 y - t|| / ||t|| is asserted below 1e-7.
-* Preconditioner application: FP64 inner 1e-8 relative (the inner GMRES iterates agree
-  to rounding, as for the one-level method), FP32 inner 2e-3, exact local solves 1e-9.
+* Preconditioner application: FP64 1e-8 relative, for inexact and exact local solves alike
+  (the inner GMRES iterates agree to rounding, as for the one-level method; the coarse
+  solve's difference, up to 1e-10 relative on medium, reaches z through M_1 A and is
+  measured at 2.3e-9 with exact local solves), FP32 inner 2e-3.
 * Solves: outer counts within one of the oracle's (tests/golden/oracle_counts.json,
   written from the oracle alone by tests/golden/make_golden.py --two-level), true
-  relative residual <= 1e-6.
+  relative residual <= 1e-6.  Where the coarse grid is too coarse to resolve the waves
+  (small, M = 8: 2.5 points per wavelength) the count reacts to the coarse solve's
+  rounding: the oracle's own count moves from 20 to 22 (exact local solves) when its
+  coarse solutions are perturbed by 1e-12 relative, about the difference between the
+  cyclic reduction and a pivoted LU on that grid (4.5e-13 measured).  The golden file
+  records that spread for the small cases, and the bound is one outside it.
 """
 
 import json
@@ -114,7 +121,7 @@ def test_two_level_apply(torch, name, m, prec, solver):
         z = to_np(gpu.apply_preconditioner(to_gpu(torch, r)))
         mode = "direct" if solver == "direct" else "deflated"
         zr = T.apply(r, mode, w.inner_tol, 100)
-        tol = {64: 1e-8, 32: 2e-3}[prec] if solver == "deflated" else 1e-9
+        tol = {64: 1e-8, 32: 2e-3}[prec]
         assert np.linalg.norm(z - zr) <= tol * np.linalg.norm(zr)
 
 
@@ -130,11 +137,12 @@ def test_two_level_solve_counts(torch, name, m):
             u, st = gpu.solve(to_gpu(torch, f))
             rel = np.linalg.norm(f - S.A @ to_np(u)) / np.linalg.norm(f)
             ref = gold["direct_outer_iters"] if solver == "direct" else gold["outer_iters"]
+            spread = [ref] + gold.get("coarse_perturbed_outer", {}).get(solver, [])
             print(name, m, prec, solver, "graph" if graph else "eager", "gpu", st["outer_iters"], "oracle", ref,
-                  "relres", rel, "ms_coarse", st["ms_coarse"], flush=True)
+                  "perturbed", spread[1:], "relres", rel, "ms_coarse", st["ms_coarse"], flush=True)
             assert st["status"] == "DD_OK" and rel <= 1e-6
             if prec == 64:
-                assert abs(st["outer_iters"] - ref) <= 1
+                assert min(spread) - 1 <= st["outer_iters"] <= max(spread) + 1
             assert st["coarse_bytes"] > 0
 
 
@@ -154,3 +162,25 @@ def test_two_level_with_guess_network(torch):
         assert st["status"] == "DD_OK" and rel <= 1e-6
         gpu.set_guess(None)
     net.close()
+
+
+def test_two_level_large_counts(torch):
+    """Full-size two-level solve (k=200, N=637, 16 x 16 perturbed subdomains, M = N/2 = 318,
+    the coarse spacing of the bench leg): FP64 inexact and exact local solves against the
+    oracle's counts; the chosen complex64 form converges."""
+    from oracle import fem
+    from paper_2103_17081_amd import inputs
+    _case("two-level large", 318)
+    gold = _gold("large", 318)
+    w = inputs.workload("large")
+    A = fem.helmholtz_matrix(w.k, w.n)
+    f = w.rhs[0]
+    for prec, solver in ((64, "deflated"), (64, "direct"), (32, "deflated")):
+        with solver_for("large", precision=prec, coarse_intervals=318, local_solver=solver) as gpu:
+            u, st = gpu.solve(to_gpu(torch, f))
+            rel = np.linalg.norm(f - A @ to_np(u)) / np.linalg.norm(f)
+            ref = gold["direct_outer_iters"] if solver == "direct" else gold["outer_iters"]
+            print("large 318", prec, solver, "gpu", st["outer_iters"], "oracle", ref, "relres", rel, flush=True)
+            assert st["status"] == "DD_OK" and rel <= 1e-6
+            if prec == 64:
+                assert abs(st["outer_iters"] - ref) <= 1
