@@ -70,6 +70,8 @@ def parse():
                     help="skip the two-level solve (global coarse space of --coarse-intervals per edge)")
     ap.add_argument("--coarse-intervals", type=int, default=0,
                     help="coarse intervals per edge of the two-level leg (0: N / 2, i.e. H = 2h)")
+    ap.add_argument("--two-level-only", action="store_true",
+                    help="run only the two-level leg and print it (profiling of the coarse correction)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-outer", type=int, default=40, help="outer iterations of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -124,6 +126,46 @@ def cpu_baseline(w, outer: int):
                       f"in {dt:.1f} s; setup excluded; BLAS threads {threads or 'default'}"}
 
 
+def two_level_leg(torch, w, f, M: int, t_one_level=None, direct: bool = True):
+    """The two-level method (global coarse space of M intervals per edge) in the chosen
+    form, and with exact subdomain solves; t_one_level (s) gives the speedups."""
+    t0 = time.perf_counter()
+    two = make_solver(w, 32, coarse_intervals=M)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    two.autotune(None)
+    t2, u2, s2 = timed_solves(torch, two, f, 1, 1)
+    two.set_graph(False)
+    _, ti = two.solve(f)
+    torch.cuda.synchronize()
+    ap2 = max(ti["precond_applies"], 1)
+    ms_c = ti["ms_coarse"] / ap2
+    ach = ti["coarse_bytes"] / (ms_c * 1e-3) / 1e9 if ms_c > 0 else 0.0
+    out = {
+        "coarse_intervals": M, "coarse_unknowns": two.nglobal_coarse, "setup_s": t_setup,
+        "time_to_solution_s": t2, "outer_iters": s2[-1]["outer_iters"],
+        "precond_applies": s2[-1]["precond_applies"],
+        "subdomain_solves_per_s": s2[-1]["subdomain_solves"] / t2,
+        "avg_inner_iters": s2[-1]["inner_iters_total"] / max(s2[-1]["subdomain_solves"], 1),
+        "true_relres": true_relres(torch, two, f, u2), "status": s2[-1]["status"],
+        "speedup_vs_one_level": t_one_level / t2 if t_one_level else None,
+        "coarse_correction": {"ms_per_apply": ms_c, "solve_bytes": ti["coarse_bytes"],
+                              "achieved_GBs_vs_solve_bytes": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS},
+        "ms_phase_instrumented_solve": {"coarse": ti["ms_coarse"], "inner": ti["ms_inner"],
+                                        "spmv": ti["ms_spmv"], "orth": ti["ms_orth"],
+                                        "all_steps": ti["ms_steps"]}}
+    two.close()
+    if direct:
+        twod = make_solver(w, 64, "direct", coarse_intervals=M)
+        t3, u3, s3 = timed_solves(torch, twod, f, 1, 1)
+        out["with_direct_local_solves"] = {
+            "time_to_solution_s": t3, "outer_iters": s3[-1]["outer_iters"],
+            "true_relres": true_relres(torch, twod, f, u3), "status": s3[-1]["status"],
+            "speedup_vs_one_level": t_one_level / t3 if t_one_level else None}
+        twod.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -142,6 +184,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.two_level_only:
+        M = args.coarse_intervals or default_coarse_intervals(w)
+        print(json.dumps({"two_level": two_level_leg(torch, w, f, M, direct=not args.no_direct)}), flush=True)
+        return 0
     chosen = make_solver(w, 32)
     tune_report = chosen.autotune(None)      # launch configuration measured on this problem (set-up)
     t, u, stats = timed_solves(torch, chosen, f, args.steps, args.warmup)
@@ -227,42 +273,8 @@ def main():
             "algorithmic_GB_per_apply": di["inner_bytes"] / max(di["precond_applies"], 1) / 1e9}
         direct.close()
     if not args.no_two_level:
-        # the two-level method (global coarse space) the paper proposes as the next step
-        M = args.coarse_intervals or default_coarse_intervals(w)
-        t0 = time.perf_counter()
-        two = make_solver(w, 32, coarse_intervals=M)
-        torch.cuda.synchronize()
-        t_setup = time.perf_counter() - t0
-        two.autotune(None)
-        t2, u2, s2 = timed_solves(torch, two, f, 1, 1)
-        two.set_graph(False)
-        _, ti = two.solve(f)
-        torch.cuda.synchronize()
-        ap2 = max(ti["precond_applies"], 1)
-        ms_c = ti["ms_coarse"] / ap2
-        ach = ti["coarse_bytes"] / (ms_c * 1e-3) / 1e9 if ms_c > 0 else 0.0
-        out["two_level"] = {
-            "coarse_intervals": M, "coarse_unknowns": two.nglobal_coarse, "setup_s": t_setup,
-            "time_to_solution_s": t2, "outer_iters": s2[-1]["outer_iters"],
-            "precond_applies": s2[-1]["precond_applies"],
-            "subdomain_solves_per_s": s2[-1]["subdomain_solves"] / t2,
-            "avg_inner_iters": s2[-1]["inner_iters_total"] / max(s2[-1]["subdomain_solves"], 1),
-            "true_relres": true_relres(torch, two, f, u2), "status": s2[-1]["status"],
-            "speedup_vs_one_level": (t / args.steps) / t2,
-            "coarse_correction": {"ms_per_apply": ms_c, "solve_bytes": ti["coarse_bytes"],
-                                  "achieved_GBs_vs_solve_bytes": ach, "frac_of_hbm_peak": ach / HBM_PEAK_GBS},
-            "ms_phase_instrumented_solve": {"coarse": ti["ms_coarse"], "inner": ti["ms_inner"],
-                                            "spmv": ti["ms_spmv"], "orth": ti["ms_orth"],
-                                            "all_steps": ti["ms_steps"]}}
-        two.close()
-        # the same two-level method with exact (FP64 block-LU) subdomain solves
-        twod = make_solver(w, 64, "direct", coarse_intervals=M)
-        t3, u3, s3 = timed_solves(torch, twod, f, 1, 1)
-        out["two_level"]["with_direct_local_solves"] = {
-            "time_to_solution_s": t3, "outer_iters": s3[-1]["outer_iters"],
-            "true_relres": true_relres(torch, twod, f, u3), "status": s3[-1]["status"],
-            "speedup_vs_one_level": (t / args.steps) / t3}
-        twod.close()
+        out["two_level"] = two_level_leg(torch, w, f, args.coarse_intervals or default_coarse_intervals(w),
+                                         t / args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_outer)
     print(json.dumps(out), flush=True)
