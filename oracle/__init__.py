@@ -23,6 +23,8 @@ schwarz    Restricted additive Schwarz preconditioner (eq. 3) with direct or
 coarse_space  Two-level variant (the step after the one-level method, Sec. 4): a global
            coarse space of piecewise-linear hats on a coarse grid of fine-grid lines,
            E_0 = Z_0^T A Z_0, and the deflation-type combination with eq. 3.
+ilu        ILU(0) factorisation and ILU(0)-preconditioned GMRES local solves, the
+           comparison of Sec. 3, Table 5.
 cnn        float64 reference of the learned-initial-guess network (forward and
            backward), checked against finite differences.
 

@@ -11,7 +11,8 @@ Test infrastructure only.  Follows the paper step by step:
   the local solution is recovered as u_j = Q_j f_j + x - Q_j B_j x.  The stopping test
   is ||P_j (f_j - B_j x)|| <= tol * ||P_j f_j||, relative to the zero-guess residual
   even when a guess is supplied (the paper only says "relative residual").
-  A direct mode replaces the subdomain GMRES by a sparse LU solve (Sec. 3, Table 1).
+  A direct mode replaces the subdomain GMRES by a sparse LU solve (Sec. 3, Table 1), an
+  "ilu" mode by GMRES preconditioned with ILU(0) (Sec. 3, Table 5; oracle/ilu.py).
 * Sec. 3: the outer solver is FGMRES with relative tolerance 1e-6 from a zero guess.
   The outer count is the number of preconditioner applications; the average inner
   count is the total inner iterations over all subdomain solves of the run.
@@ -51,11 +52,19 @@ class Subdomain:
         self.B = B.tocsr()
         self.defl = dfl.Deflation(self.B, dfl.z2d(geom.nx, geom.ny, prob.deflation))
         self._lu = None
+        self._ilu = None
 
     def direct(self, f: np.ndarray) -> np.ndarray:
         if self._lu is None:
             self._lu = spla.splu(self.B.tocsc())
         return self._lu.solve(f)
+
+    def ilu_gmres(self, f: np.ndarray, tol: float, maxit: int):
+        """ILU(0)-preconditioned GMRES local solve (Sec. 3, Table 5): (u, iterations)."""
+        if self._ilu is None:
+            from .ilu import Ilu0Solver
+            self._ilu = Ilu0Solver(self.B)
+        return self._ilu.solve(f, tol, maxit)
 
     def deflated_gmres(self, f: np.ndarray, tol: float, maxit: int, guess=None):
         """Inexact local solve; returns (u, iterations, accepted_guess)."""
@@ -118,6 +127,10 @@ class Schwarz:
             if mode == "direct":
                 us.append(s.direct(f))
                 its.append(0)
+            elif mode == "ilu":
+                u, it = s.ilu_gmres(f, tol, maxit)
+                us.append(u)
+                its.append(it)
             else:
                 g = None if guesses is None else guesses[j]
                 u, it, _ = s.deflated_gmres(f, tol, maxit, g)
