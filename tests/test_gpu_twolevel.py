@@ -184,3 +184,83 @@ def test_two_level_large_counts(torch):
             assert st["status"] == "DD_OK" and rel <= 1e-6
             if prec == 64:
                 assert abs(st["outer_iters"] - ref) <= 1
+
+
+def test_two_level_exact_coarse_space(torch):
+    """M = N: Z_0 is the identity, E_0 = A, the preconditioner is A^{-1} up to the coarse
+    solve's rounding, and FGMRES stops after one iteration (as the oracle's pin)."""
+    _case("two-level exact coarse space")
+    w, S = oracle_for("small")
+    f = w.rhs[0]
+    with solver_for("small", precision=64, coarse_intervals=w.n) as gpu:
+        u, st = gpu.solve(to_gpu(torch, f))
+        rel = np.linalg.norm(f - S.A @ to_np(u)) / np.linalg.norm(f)
+        print("outer", st["outer_iters"], "relres", rel, flush=True)
+        assert st["status"] == "DD_OK" and st["outer_iters"] == 1 and rel <= 1e-9
+
+
+def test_two_level_single_coarse_unknown(torch):
+    """M = 2: one coarse unknown (a single block row of size one in the reduction)."""
+    from oracle import coarse_space
+    _case("two-level M=2")
+    w, S = oracle_for("small")
+    T = coarse_space.TwoLevel(S, 2)
+    with solver_for("small", precision=64, outer_maxit=10, coarse_intervals=2) as gpu:
+        assert gpu.nglobal_coarse == 1
+        r = crandn(np.random.default_rng(5), S.ndof)
+        z = to_np(gpu.apply_preconditioner(to_gpu(torch, r)))
+        zr = T.apply(r, "deflated", w.inner_tol, 100)
+        assert np.linalg.norm(z - zr) <= 1e-8 * np.linalg.norm(zr)
+
+
+def _rhs_set(w, S, rng, count):
+    from paper_2103_17081_amd import inputs
+    fs = [w.rhs[0], np.zeros(S.ndof, dtype=np.complex128)]
+    while len(fs) < count:
+        fs.append(inputs.gaussian_load(w.n, inputs.gaussian_params(rng)) +
+                  inputs.point_source(w.n, tuple(rng.uniform(0.1, 0.9, 2))))
+    return fs
+
+
+def test_two_level_multi_rhs_matches_single(torch):
+    """Nine right-hand sides (two groups of the coarse solve kernel, 8 + 1) advance together;
+    each matches its own single-rhs two-level solve, the zero one stops at once."""
+    _case("two-level multi rhs")
+    w, S = oracle_for("small")
+    fs = _rhs_set(w, S, np.random.default_rng(23), 9)
+    singles = []
+    with solver_for("small", precision=64, coarse_intervals=16) as g1:
+        for f in fs:
+            u, st = g1.solve(to_gpu(torch, f))
+            singles.append((to_np(u), st))
+    with solver_for("small", precision=64, coarse_intervals=16, nrhs=len(fs)) as gm:
+        U, st = gm.solve(to_gpu(torch, np.stack(fs)))
+        U = to_np(U)
+    assert st["status"] == "DD_OK"
+    for q, (f, (u1, s1)) in enumerate(zip(fs, singles)):
+        if not np.any(f):
+            assert not np.any(U[q])
+            continue
+        rel = np.linalg.norm(f - S.A @ U[q]) / np.linalg.norm(f)
+        assert rel <= 1e-6, (q, rel)
+        np.testing.assert_allclose(U[q], u1, rtol=0, atol=1e-12 * np.abs(u1).max())
+    assert st["outer_iters"] == max(s["outer_iters"] for _, s in singles)
+
+
+def test_two_level_multi_rhs_apply_large(torch):
+    """Nine right-hand sides through the large coarse solve (its 64-row launches included):
+    the batched application equals nine single applications."""
+    from paper_2103_17081_amd import inputs
+    _case("two-level multi rhs apply large")
+    w = inputs.workload("large")
+    rng = np.random.default_rng(29)
+    nd = (w.n - 1) ** 2
+    R = np.stack([crandn(rng, nd) for _ in range(9)])
+    singles = []
+    with solver_for("large", precision=64, coarse_intervals=318, outer_maxit=10) as g1:
+        for q in range(9):
+            singles.append(to_np(g1.apply_preconditioner(to_gpu(torch, R[q]))))
+    with solver_for("large", precision=64, coarse_intervals=318, outer_maxit=10, nrhs=9) as gm:
+        Z = to_np(gm.apply_preconditioner(to_gpu(torch, R)))
+    for q in range(9):
+        np.testing.assert_allclose(Z[q], singles[q], rtol=0, atol=1e-12 * np.abs(singles[q]).max())
