@@ -87,7 +87,7 @@ typedef struct {
                           linear deflation of eq. 5); E_0 = Z_0^T A Z_0 factored exactly (FP64
                           block cyclic reduction); each application is
                           M^{-1} r = M_1^{-1} (r - A Q_0 r) + Q_0 r, Q_0 = Z_0 E_0^{-1} Z_0^T, with
-                          M_1^{-1} the one-level preconditioner.  Needs M <= N and M - 1 <= 512. */
+                          M_1^{-1} the one-level preconditioner.  Needs M <= N and M - 1 <= 1024. */
 } dd_params;
 
 typedef struct {

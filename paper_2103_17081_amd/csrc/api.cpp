@@ -201,7 +201,7 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   if (p->nrhs < 1 || p->nrhs > 64) return fail(DD_EINVAL, "nrhs must be in [1, 64]");
   if (p->coarse_intervals != 0 &&
       (p->coarse_intervals < 2 || p->coarse_intervals > n || p->coarse_intervals - 1 > ddh::kMaxGlobalCoarse))
-    return fail(DD_EINVAL, "coarse_intervals must be 0 (one-level) or in [2, N] with at most 513 intervals");
+    return fail(DD_EINVAL, "coarse_intervals must be 0 (one-level) or in [2, N] with at most 1025 intervals");
   if (p->use_graph && (p->graph_steps < 1 || p->graph_steps > kMaxGraphSteps))
     return fail(DD_EINVAL, "graph_steps must be in [1, 64]");
   auto cuts = [&](const int* c, int parts, std::vector<int>& out) -> dd_status {

@@ -38,7 +38,7 @@
 
 namespace ddh {
 
-constexpr int kMaxGlobalCoarse = 512;   // largest coarse block n = M - 1
+constexpr int kMaxGlobalCoarse = 1024;  // largest coarse block n = M - 1
 constexpr int kBcrRhsGroup = 8;         // right-hand sides per pass of the solve kernel
 constexpr int kBcrTile = 64;            // rows per tile of the factors' solve layout
 

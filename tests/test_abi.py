@@ -45,7 +45,7 @@ def test_default_params():
     (dict(local_solver=5), "local_solver must be"),
     (dict(n_intervals=32, coarse_intervals=1), "coarse_intervals"),
     (dict(n_intervals=32, coarse_intervals=33), "coarse_intervals"),
-    (dict(n_intervals=1200, px=8, py=8, coarse_intervals=600), "coarse_intervals"),
+    (dict(n_intervals=2400, px=8, py=8, coarse_intervals=1100), "coarse_intervals"),
     (dict(coarse_intervals=-3), "coarse_intervals"),
 ])
 def test_invalid_parameters_rejected_on_host(kw, needle):

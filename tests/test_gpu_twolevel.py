@@ -264,3 +264,28 @@ def test_two_level_multi_rhs_apply_large(torch):
         Z = to_np(gm.apply_preconditioner(to_gpu(torch, R)))
     for q in range(9):
         np.testing.assert_allclose(Z[q], singles[q], rtol=0, atol=1e-12 * np.abs(singles[q]).max())
+
+
+def test_global_coarse_xlarge(torch):
+    """The largest one-GPU grid (k=400, N=1274) with M = N/2 = 637: 404,496 coarse unknowns,
+    block rows of 636 (above the 512 of the large grid).  E_0 on sampled rows against the
+    oracle's Galerkin product; the cyclic-reduction solve's residual with the oracle's E_0."""
+    _case("global coarse xlarge", 637)
+    w, C = _coarse_oracle("xlarge", 637)
+    nc = 636
+    with solver_for("xlarge", outer_maxit=2, coarse_intervals=637) as gpu:
+        coef, piv = gpu.global_coarse_matrix()
+        assert piv > 0
+        rng = np.random.default_rng(637)
+        E = sp.csr_matrix(C.E.real)
+        for c in rng.choice(nc * nc, 500, replace=False):
+            cx, cy = c % nc, c // nc
+            for o in range(9):
+                qx, qy = cx + o % 3 - 1, cy + o // 3 - 1
+                ref = E[c, qy * nc + qx] if (0 <= qx < nc and 0 <= qy < nc) else 0.0
+                assert abs(coef[c, o] - ref) <= 1e-13 * abs(E).max()
+        t = crandn(rng, nc * nc)
+        y = to_np(gpu.op_global_coarse_solve(to_gpu(torch, t)))
+        rel = np.linalg.norm(C.E @ y - t) / np.linalg.norm(t)
+        print("xlarge coarse solve rel. residual", rel, flush=True)
+        assert np.all(np.isfinite(y)) and rel <= 1e-7
