@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(256) dots2_kernel(const cplx<double>* __restri
 #pragma unroll
       for (int r = 0; r < kD2Rows; ++r) {
         const long long n = n0 + r * 256;
-        v[q][r] = (q < cnt && n < ndof) ? Vb[(long long)(s0 + q) * ndof + n] : czero<double>();
+        v[q][r] = (q < cnt && n < ndof) ? load_stream(Vb + (long long)(s0 + q) * ndof + n) : czero<double>();
       }
     }
     double pv[kD2Vals];
@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(256) dcgs2_update_kernel(cplx<double>* __restr
 #pragma unroll
         for (int r = 0; r < kRowsPerThread; ++r) {
           const long long n = n0 + r * 256;
-          vv[q][r] = (q0 + q < s1 && n < ndof) ? V[(long long)(q0 + q) * ndof + n] : czero<double>();
+          vv[q][r] = (q0 + q < s1 && n < ndof) ? load_stream(V + (long long)(q0 + q) * ndof + n) : czero<double>();
         }
       }
 #pragma unroll
