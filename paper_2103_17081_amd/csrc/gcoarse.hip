@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) gc_gemm_kernel(const GemmTask* __restrict
 
 // Inverse of a work block into the factor array: copy, then Gauss-Jordan with partial
 // pivoting in place (one workgroup per task).  pivmin[task] = smallest |pivot|.
-constexpr int kInvThreads = 512;
+constexpr int kInvThreads = 1024;
 __global__ void __launch_bounds__(kInvThreads) gc_inverse_kernel(const InvTask* __restrict__ tasks,
                                                                  const double* __restrict__ work, double* fac,
                                                                  int n, double* __restrict__ pivmin) {
