@@ -38,11 +38,23 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "DD-FGMRES time-to-solution (rel res 1e-6) & subdomain solves/s, chosen vs plain"
 
 
-def recorded_traffic():
-    """Calibrated HBM bytes per dispatch from the committed counter summary, if the kernel
-    sources are unchanged since the counters were taken (else {})."""
-    import glob
+# Sources of the kernels whose HBM counters profiles/large_solve_hbm_traffic.md records.
+TRAFFIC_SOURCES = ["inner_kernels.hip", "outer_kernels.hip", "kernels.hpp", "coarse.hpp", "stencil.hpp", "outer.hpp",
+                   "common.hpp"]
+
+
+def sources_sha256() -> str:
     import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(ROOT, "paper_2103_17081_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """Calibrated HBM bytes per dispatch from the committed counter summary, if the sources
+    of the profiled kernels are unchanged since the counters were taken (else {})."""
     path = os.path.join(ROOT, "profiles", "large_solve_hbm_traffic.md")
     if not os.path.exists(path):
         return {}
@@ -50,11 +62,9 @@ def recorded_traffic():
     if "```json" not in text:
         return {}
     block = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2103_17081_amd", "csrc", "*"))):
-        h.update(os.path.basename(p).encode())
-        h.update(open(p, "rb").read())
-    return block["traffic_bytes_per_dispatch"] if h.hexdigest() == block["csrc_sha256"] else {}
+    if block.get("sources") != TRAFFIC_SOURCES or block.get("sources_sha256") != sources_sha256():
+        return {}
+    return block["traffic_bytes_per_dispatch"]
 
 
 def parse():
