@@ -4,6 +4,7 @@ Usage: python tests/golden/make_golden.py small [medium] [large]
        python tests/golden/make_golden.py --spread small [medium]
        python tests/golden/make_golden.py --direct small [medium] [large]
        python tests/golden/make_golden.py --two-level small:16 [medium:80]
+       python tests/golden/make_golden.py --paper-two-level
 
 For each named workload (paper_2103_17081_amd.inputs.workload) and its first right-hand
 side, runs the oracle's outer FGMRES with impedance (ORAS) local matrices, linear
@@ -13,6 +14,10 @@ residual.  Existing entries for other workloads are kept.  --direct records, und
 "direct", the same run with exact (sparse LU) subdomain solves.  --two-level NAME:M
 records, under "two_level" -> "M", the oracle's two-level method (global coarse space of
 M coarse intervals per edge) with deflated-GMRES and with exact subdomain solves.
+--paper-two-level writes paper_mesh_two_level.json: the paper's variant in its mesh mode
+(Dirichlet local matrices, Bezier deflation, k = 20 and 40 at 10 points per wavelength,
+N = 4, 9, 16, 25) without and with the global coarse space (M = n/2), and the two-level
+counts' spread under coarse solutions perturbed by 1e-12 relative.
 """
 
 import json
@@ -144,9 +149,40 @@ def two_level(specs):
             json.dump(data, fh, indent=1, sort_keys=True)
 
 
+def paper_two_level():
+    import numpy as np
+    from oracle import coarse_space
+    rows = []
+    for k, nglob in ((20, 30), (40, 60)):
+        n = nglob + 1
+        f = inputs.point_source(n)
+        for N in (4, 9, 16, 25):
+            P = int(round(N ** 0.5))
+            cuts = inputs.uniform_cuts(n, P)
+            S = schwarz.Schwarz(schwarz.Problem(float(k), n, cuts, cuts, 1, "dirichlet", "bezier"))
+            _, s1 = S.solve(f, mode="deflated", inner_tol=1e-2)
+            T = coarse_space.TwoLevel(S, n // 2)
+            _, s2 = T.solve(f, mode="deflated", inner_tol=1e-2)
+            exact = T.coarse.coarse_solve
+            spread = []
+            for sd in range(4):
+                rng = np.random.default_rng(3000 + sd)
+                T.coarse.coarse_solve = lambda t, r=rng: (lambda y: y * (1 + 1e-12 * r.standard_normal(y.size)))(exact(t))
+                _, sp_ = T.solve(f, mode="deflated", inner_tol=1e-2)
+                spread.append(sp_.outer_iters)
+            T.coarse.coarse_solve = exact
+            rows.append({"k": k, "n_glob": nglob, "N": N, "M": n // 2, "one_level": s1.outer_iters,
+                         "two_level": s2.outer_iters, "two_level_perturbed": spread})
+            print(rows[-1], flush=True)
+    with open(os.path.join(HERE, "paper_mesh_two_level.json"), "w") as fh:
+        json.dump({"source": "oracle (tests/golden/make_golden.py --paper-two-level)", "rows": rows}, fh, indent=1)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
-    if args and args[0] == "--two-level":
+    if args and args[0] == "--paper-two-level":
+        paper_two_level()
+    elif args and args[0] == "--two-level":
         two_level(args[1:] or ["small:16"])
     elif args and args[0] == "--direct":
         direct(args[1:] or ["small"])
