@@ -9,8 +9,9 @@ with widths perturbed by +-25%, three seeded Gaussian sources, inner tolerance 1
 
 `value` is whole-job throughput in subdomain solves per second of the chosen form
 (complex64 subdomain Krylov work, FP64 coarse solves and outer FGMRES, outer steps
-replayed from a captured hipGraph); `ms_per_step` is its time to solution.  The all-FP64 ("plain") form is timed beside
-it.  `kernels` gives, for the batched subdomain-solve kernel and the two basis sweeps
+replayed from a captured hipGraph, autotuned launch configuration); `ms_per_step` is its
+time to solution.  The plain form (complex128 subdomain Krylov work, default launch
+configuration, outer steps launched one by one) is timed beside it.  `kernels` gives, for the batched subdomain-solve kernel and the two basis sweeps
 of the outer delayed-CGS2 Arnoldi, algorithmic bytes (counted per launch by the
 library) over durations from HIP events recorded on the library's stream around each
 kernel, in one more solve of the same handle and inputs with the steps launched one
@@ -258,14 +259,17 @@ def main():
     }
     chosen.close()
     if not args.no_plain:
+        # plain: complex128 subdomain Krylov work, default launch configuration (no
+        # autotuning), outer steps launched one by one (no graph replay)
         plain = make_solver(w, 64)
-        plain.autotune(None)
+        plain.set_graph(False)
         tp, up, sp = timed_solves(torch, plain, f, 1, 1)
         out["plain"] = {"time_to_solution_s": tp, "outer_iters": sp[-1]["outer_iters"],
                         "subdomain_solves_per_s": sp[-1]["subdomain_solves"] / tp,
                         "avg_inner_iters": sp[-1]["inner_iters_total"] / max(sp[-1]["subdomain_solves"], 1),
                         "true_relres": true_relres(torch, plain, f, up), "status": sp[-1]["status"],
-                        "graph_replays": sp[-1]["graph_replays"]}
+                        "graph_replays": sp[-1]["graph_replays"],
+                        "form": "complex128 inner, default launch configuration, steps launched one by one"}
         out["chosen_speedup_vs_plain"] = tp / (t / args.steps)
         plain.close()
     if not args.no_direct:
