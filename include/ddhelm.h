@@ -112,7 +112,8 @@ typedef struct {
                                   inside a graph replay) */
   /* Algorithmic bytes of the subdomain-solve kernel summed over its launches: per solve,
      gather 16 n_j + scatter 16 owned_j (32 when the two-level correction is added) +
-     (k_j + 2) coarse-factor reads of 16 ((2 my - 1) mx^2 + 3 mx my) bytes + Krylov traffic s n_j (2 k_j + 2 k_j (k_j + 1))
+     (k_j + 1) coarse-factor reads of 16 ((2 my - 1) mx^2 + 3 mx my) bytes + the coarse vectors kept for the
+     recovery 16 nc (2 k_j + 2) + Krylov traffic s n_j (2 k_j + 2 k_j (k_j + 1))
      (basis writes, CGS2 reads, final combination) + local rhs write/read 2 s n_j, with
      s = 8 (FP32) or 16 bytes per complex value. */
   double inner_bytes;

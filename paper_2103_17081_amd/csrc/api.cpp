@@ -78,6 +78,7 @@ struct dd_handle {
   void* U = nullptr;
   void* V = nullptr;
   cplx<double>* R = nullptr;
+  cplx<double>* Sc = nullptr;   // coarse vectors kept by each subdomain solve for its recovery
   int* iters = nullptr;
   int* flags = nullptr;
   unsigned long long* counters = nullptr;
@@ -328,6 +329,7 @@ ddh::InnerArgs<T> inner_args(dd_handle* h) {
   a.X = (cplx<T>*)h->X;
   a.V = (cplx<T>*)h->V;
   a.R = h->R;
+  a.Sc = h->Sc;
   a.iters = h->iters;
   a.flags = h->flags;
   a.counters = h->counters;
@@ -518,6 +520,7 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     if (h->prec == 32) DD_TRY(alloc_inner<float>(h));
     else DD_TRY(alloc_inner<double>(h));
     DD_TRY(h->alloc(&h->R, (size_t)h->nsub * h->nrhs * h->maxit * h->maxit));
+    DD_TRY(h->alloc(&h->Sc, (size_t)h->nsub * h->nrhs * (h->maxit + 2) * h->max_nc));
     DD_TRY(h->alloc(&h->iters, (size_t)h->nsub * h->nrhs));
     DD_TRY(h->alloc(&h->flags, (size_t)h->nsub * h->nrhs));
     DD_TRY(h->alloc(&h->counters, 5));

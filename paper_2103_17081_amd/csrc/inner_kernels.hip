@@ -13,6 +13,9 @@
 //   Arnoldi on w = P B v (deflated operator), classical Gram-Schmidt applied twice;
 //   stop when the least-squares residual estimate <= tol * ||P f||;
 //   x = x0 + V y,  u = x + Z E^{-1} Z^T (f - B x)   (so f - B u = P (f - B x));
+//   the coarse vector of the recovery is assembled from those the solve already formed,
+//   E^{-1} Z^T (f - B x) = E^{-1} Z^T f - E^{-1} Z^T B x0 - sum_i y_i E^{-1} Z^T B v_i,
+//   so it costs no deflated application of its own;
 //   z(owned nodes of j) = u.
 #include <algorithm>
 
@@ -295,6 +298,13 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   cplx<T>* X = a.X + fo;
   cplx<T>* V = a.V + fo * (maxit + 1);
   cplx<double>* R = a.R + (long long)sidx * maxit * maxit;
+  // coarse vectors kept for the recovery: slot 0 E^{-1} Z^T f, slot 1 E^{-1} Z^T B x0, slot 2 + i
+  // E^{-1} Z^T B v_i (written and read back by the same thread for each entry)
+  cplx<double>* Sc = a.Sc ? a.Sc + (long long)sidx * (maxit + 2) * a.max_nc : nullptr;
+  auto keep_coarse = [&](int slot) {
+    if (Sc)
+      for (int e = tid; e < d.ncp; e += NT) Sc[(long long)slot * a.max_nc + e] = L.ca[e];
+  };
   const int ldg = a.cs.n - 1;
   const long long jstep = a.jdev ? (long long)*a.jdev : 0;
   const cplx<double>* __restrict__ rin = a.r ? a.r + jstep * a.rslot : nullptr;
@@ -336,6 +346,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   restrict_to(d, L.B, L.ct);
   lds_barrier();
   coarse_solve<NT>(d, a.fac, L.lc, L.ct, L.ca);
+  keep_coarse(0);
   prolong_to(d, L.ca, L.A);
   lds_barrier();
   apply_B<T, true>(d, L.tab, L.A, L.B);
@@ -368,6 +379,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       }
       lds_barrier();
       deflated_op<T, NT>(d, a.fac, L);   // tile B = P B g
+      keep_coarse(1);
       for (int n = tid; n < nj; n += NT) L.B[n] = W[n] - L.B[n];
       lds_barrier();
       const double rn = tile_norm<T, NT>(d, L.B, L);
@@ -392,6 +404,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
     const int S = L.stride;
     while (!converged && k < maxit) {
       deflated_op<T, NT>(d, a.fac, L);   // tile B = P B v_k
+      keep_coarse(2 + k);
       // classical Gram-Schmidt, applied twice
       for (int pass = 0; pass < 2; ++pass) {
         basis_dots<T, NT>(V, nj, k, L.B, L.red, S, pass == 0);
@@ -484,7 +497,16 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   }
   lds_barrier();
   // recovery: u = x + Z E^{-1} Z^T (f - B x)
-  {
+  if (Sc) {
+    // from the kept coarse vectors (y_i in L.h)
+    for (int e = tid; e < d.ncp; e += NT) {
+      cplx<double> c = Sc[e];
+      if (accepted) c = c - Sc[a.max_nc + e];
+      for (int i = 0; i < k; ++i) c = c - L.h[i] * Sc[(long long)(2 + i) * a.max_nc + e];
+      L.ca[e] = c;
+    }
+    lds_barrier();
+  } else {
     const int ny = d.ny;
     for (int n = tid; n < nj; n += NT) {
       const int lj = n / nx, li = n - lj * nx;
@@ -502,11 +524,11 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       }
       L.B[n] = fmul * F[n] - acc;
     }
+    lds_barrier();
+    restrict_to(d, L.B, L.ct);
+    lds_barrier();
+    coarse_solve<NT>(d, a.fac, L.lc, L.ct, L.ca);
   }
-  lds_barrier();
-  restrict_to(d, L.B, L.ct);
-  lds_barrier();
-  coarse_solve<NT>(d, a.fac, L.lc, L.ct, L.ca);
   for (int n = tid; n < nj; n += NT) {
     const int lj = n / nx, li = n - lj * nx;
     const cplx<T> u = L.A[n] + ccast<T>(prolong_at(d, L.ca, li, lj));
@@ -531,9 +553,11 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       const unsigned long long s = sizeof(cplx<T>), nn = (unsigned long long)nj, kk = (unsigned long long)k;
       const unsigned long long own = (unsigned long long)(d.oi1 - d.oi0 + 1) * (d.oj1 - d.oj0 + 1);
       const unsigned long long fac_bytes = 16ull * (unsigned long long)coarse_solve_values(d);
-      unsigned long long bytes = 16ull * nn + (a.zadd ? 32ull : 16ull) * own + (kk + 2) * fac_bytes +
+      const unsigned long long ncp = (unsigned long long)d.ncp;
+      unsigned long long bytes = 16ull * nn + (a.zadd ? 32ull : 16ull) * own +
+                                 (Sc ? (kk + 1) * fac_bytes + 16ull * ncp * (2 * kk + 2) : (kk + 2) * fac_bytes) +
                                  s * nn * (2 * kk + 2 * kk * (kk + 1)) + 2 * s * nn;
-      if (offered) bytes += fac_bytes + (a.gtile ? 8ull : s) * nn + 3 * s * nn;
+      if (offered) bytes += fac_bytes + (a.gtile ? 8ull : s) * nn + 3 * s * nn + (Sc ? 32ull * ncp : 0ull);
       atomicAdd(a.counters + 4, bytes);
     }
   }
