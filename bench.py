@@ -10,9 +10,12 @@ with widths perturbed by +-25%, three seeded Gaussian sources, inner tolerance 1
 `value` is whole-job throughput in subdomain solves per second of the chosen form
 (complex64 subdomain Krylov work, FP64 coarse solves and outer FGMRES, outer steps
 replayed from a captured hipGraph, autotuned launch configuration); `ms_per_step` is its
-time to solution.  The plain form (complex128 subdomain Krylov work, default launch
-configuration, outer steps launched one by one) is timed beside it.  `kernels` gives, for the batched subdomain-solve kernel and the two basis sweeps
-of the outer delayed-CGS2 Arnoldi, algorithmic bytes (counted per launch by the
+time to solution.  The plain form (complex128 subdomain Krylov work as one batched launch
+per GMRES stage with the inner loop on the host, no persistent kernel, outer steps launched
+one by one) is timed beside it, and `fused_fp64` times the complex128 subdomain GMRES inside
+the fused kernel (steps one by one), separating the gain of fusion from that of precision.
+`kernels` gives, for the batched subdomain-solve kernel and the two basis sweeps of the
+outer delayed-CGS2 Arnoldi, algorithmic bytes (counted per launch by the
 library) over durations from HIP events recorded on the library's stream around each
 kernel, in one more solve of the same handle and inputs with the steps launched one
 by one right after the timed solves (HIP cannot time events inside graph replays);
@@ -90,11 +93,13 @@ def parse():
     return ap.parse_args()
 
 
-def make_solver(w, precision: int, local_solver: str = "deflated", coarse_intervals: int = 0):
+def make_solver(w, precision: int, local_solver: str = "deflated", coarse_intervals: int = 0,
+                inner_launch: str = "fused"):
     from paper_2103_17081_amd.binding import Solver
     return Solver(w.k, n_intervals=w.n, cuts_x=w.cuts_x, cuts_y=w.cuts_y, overlap=w.overlap,
                   inner_precision=precision, inner_tol=w.inner_tol, outer_tol=w.outer_tol,
-                  outer_maxit=4000, local_solver=local_solver, coarse_intervals=coarse_intervals)
+                  outer_maxit=4000, local_solver=local_solver, coarse_intervals=coarse_intervals,
+                  inner_launch=inner_launch, use_graph=inner_launch == "fused")
 
 
 def default_coarse_intervals(w) -> int:
@@ -259,19 +264,30 @@ def main():
     }
     chosen.close()
     if not args.no_plain:
-        # plain: complex128 subdomain Krylov work, default launch configuration (no
-        # autotuning), outer steps launched one by one (no graph replay)
-        plain = make_solver(w, 64)
-        plain.set_graph(False)
+        # plain: complex128 subdomain Krylov work as one batched launch per GMRES stage (all
+        # subdomains per launch) with the inner loop on the host, no persistent kernel, outer
+        # steps launched one by one (no graph replay)
+        plain = make_solver(w, 64, inner_launch="multi")
         tp, up, sp = timed_solves(torch, plain, f, 1, 1)
         out["plain"] = {"time_to_solution_s": tp, "outer_iters": sp[-1]["outer_iters"],
                         "subdomain_solves_per_s": sp[-1]["subdomain_solves"] / tp,
                         "avg_inner_iters": sp[-1]["inner_iters_total"] / max(sp[-1]["subdomain_solves"], 1),
                         "true_relres": true_relres(torch, plain, f, up), "status": sp[-1]["status"],
-                        "graph_replays": sp[-1]["graph_replays"],
-                        "form": "complex128 inner, default launch configuration, steps launched one by one"}
+                        "graph_replays": sp[-1]["graph_replays"], "ms_inner": sp[-1]["ms_inner"],
+                        "form": "complex128 inner, one batched launch per GMRES stage, host-driven inner "
+                                "loop, steps launched one by one"}
         out["chosen_speedup_vs_plain"] = tp / (t / args.steps)
         plain.close()
+        # the same complex128 subdomain GMRES inside the fused batched kernel (steps one by
+        # one, default launch configuration): separates the fusion from the precision
+        fused = make_solver(w, 64)
+        fused.set_graph(False)
+        tq, uq, sq = timed_solves(torch, fused, f, 1, 0)
+        out["fused_fp64"] = {"time_to_solution_s": tq, "outer_iters": sq[-1]["outer_iters"],
+                             "true_relres": true_relres(torch, fused, f, uq), "status": sq[-1]["status"],
+                             "ms_inner": sq[-1]["ms_inner"],
+                             "form": "complex128 inner in the fused batched kernel, steps launched one by one"}
+        fused.close()
     if not args.no_direct:
         # the paper's direct-solve baseline: exact FP64 subdomain solves (block LU of each B_j)
         direct = make_solver(w, 64, "direct")

@@ -49,6 +49,7 @@ typedef enum {
 enum { DD_LOCAL_IMPEDANCE = 0, DD_LOCAL_DIRICHLET = 1 };
 enum { DD_DEFLATION_LINEAR = 0, DD_DEFLATION_BEZIER = 1 };
 enum { DD_LOCAL_DEFLATED_GMRES = 0, DD_LOCAL_DIRECT = 1 };
+enum { DD_INNER_FUSED = 0, DD_INNER_MULTI = 1 };
 
 /* Problem and solver parameters.  Start from dd_default_params(). */
 typedef struct {
@@ -88,6 +89,14 @@ typedef struct {
                           block cyclic reduction); each application is
                           M^{-1} r = M_1^{-1} (r - A Q_0 r) + Q_0 r, Q_0 = Z_0 E_0^{-1} Z_0^T, with
                           M_1^{-1} the one-level preconditioner.  Needs M <= N and M - 1 <= 1024. */
+  int inner_launch;    /* DD_INNER_FUSED (default): every subdomain solve of a preconditioner
+                          application runs inside one batched launch (one workgroup per solve, the
+                          whole GMRES iteration in the kernel).  DD_INNER_MULTI: the plain form of
+                          the same deflated GMRES -- one batched launch per stage (stencil,
+                          restriction, coarse solve, prolongation, Gram-Schmidt pass, rotation)
+                          with the iteration loop on the host and one host synchronisation per
+                          inner iteration; needs inner_precision 64, nrhs 1, use_graph 0,
+                          inner_maxit <= 256 and no guess network. */
 } dd_params;
 
 typedef struct {
@@ -160,7 +169,9 @@ dd_status dd_solve(dd_handle* h, const void* f, void* u, void* stream, dd_stats*
 
 dd_status dd_destroy(dd_handle* h);
 /* Switch graph replay of the outer steps on or off for later dd_solve calls (the
-   per-phase event timings of dd_stats are only available with it off). */
+   per-phase event timings of dd_stats are only available with it off).  DD_EINVAL when
+   turning it on for a handle with inner_launch DD_INNER_MULTI (its host loop cannot be
+   captured). */
 dd_status dd_set_graph(dd_handle* h, int use_graph);
 /* Autotuner: time candidate launch configurations on this handle's problem with HIP events
    and keep the fastest: threads per subdomain-solve workgroup (256 or 512), launch order
@@ -168,7 +179,8 @@ dd_status dd_set_graph(dd_handle* h, int use_graph);
    cache_path (may be NULL) a line "<signature> | <choice>" is looked up first (signature:
    GPU architecture, grid, partition hash, overlap, local condition, precision, inner_maxit,
    nrhs, restart) and appended after measuring.  Uses the handle's workspaces: do not call
-   it while a solve is in flight.  report (may be NULL) receives a text summary. */
+   it while a solve is in flight.  report (may be NULL) receives a text summary.  DD_EINVAL
+   for inner_launch DD_INNER_MULTI (it has no launch configuration to tune). */
 dd_status dd_autotune(dd_handle* h, const char* cache_path, void* stream, char* report, int report_len);
 const char* dd_last_error(void);
 
@@ -210,7 +222,9 @@ dd_status dd_op_scatter(dd_handle* h, int precision, const void* u, void* z, voi
 /* Batched inexact subdomain solves in the handle's inner precision: packed f [nrhs][nfine]
    -> packed u (recovered local solutions).  guess (packed, same type) may be NULL.
    iters and flags (host int arrays of nrhs * nsub, may be NULL) receive per-solve
-   iteration counts and flags (bit 0 guess accepted, bit 1 not converged). */
+   iteration counts and flags (bit 0 guess accepted, bit 1 not converged).  With
+   inner_launch DD_INNER_MULTI the solves run in the multi-launch form and guess must be
+   NULL (DD_EINVAL otherwise). */
 dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void* u, int32_t* iters,
                             int32_t* flags, void* stream);
 
@@ -301,7 +315,7 @@ dd_status dd_net_adam(dd_net* net, double lr, double beta1, double beta2, double
    solves evaluate it on every subdomain right-hand side and offer the result as the
    initial guess.  The network is borrowed (the caller keeps it alive while attached)
    and must have tile >= every subdomain's nx, ny and max_batch >= nsub * nrhs.
-   Attaching allocates nothing. */
+   Attaching allocates nothing.  DD_EINVAL for inner_launch DD_INNER_MULTI. */
 dd_status dd_set_guess(dd_handle* h, dd_net* net);
 /* Network input tiles of all subdomain solves of global r (device complex128
    [nrhs][ndof]): x device fp32 [nsub * nrhs][T][T][4] and the scales s (device double

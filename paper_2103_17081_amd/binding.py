@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "DD_OK", 1: "DD_EINVAL", 2: "DD_ENOMEM", 3: "DD_EHIP", 4: "DD
 LOCAL_BC = {"impedance": 0, "robin": 0, "dirichlet": 1}
 DEFLATION = {"linear": 0, "bezier": 1}
 LOCAL_SOLVER = {"deflated": 0, "deflated_gmres": 0, "direct": 1}
+INNER_LAUNCH = {"fused": 0, "multi": 1}
 
 
 class Params(ctypes.Structure):
@@ -50,6 +51,7 @@ class Params(ctypes.Structure):
         ("graph_steps", ctypes.c_int),
         ("local_solver", ctypes.c_int),
         ("coarse_intervals", ctypes.c_int),
+        ("inner_launch", ctypes.c_int),
     ]
 
 
@@ -226,7 +228,7 @@ class Solver:
                  deflation: str = "linear", inner_precision: int = 64, inner_tol: float = 1e-2,
                  inner_maxit: int = 100, outer_tol: float = 1e-6, outer_maxit: int = 3000,
                  outer_restart: int = 0, nrhs: int = 1, use_graph: bool = True, graph_steps: int = 8,
-                 local_solver: str = "deflated", coarse_intervals: int = 0):
+                 local_solver: str = "deflated", coarse_intervals: int = 0, inner_launch: str = "fused"):
         p = default_params()
         p.k, p.ppwl, p.n_intervals = k, ppwl, n_intervals
         p.px, p.py = px, py
@@ -250,6 +252,7 @@ class Solver:
         p.graph_steps = graph_steps
         p.local_solver = LOCAL_SOLVER[local_solver]
         p.coarse_intervals = coarse_intervals
+        p.inner_launch = INNER_LAUNCH[inner_launch]
         self.params = p
         self._h = ctypes.c_void_p()
         torch = _torch()
@@ -556,6 +559,8 @@ def setup_status(**kw) -> tuple[int, str]:
             p.deflation = DEFLATION[val] if isinstance(val, str) else val
         elif key == "local_solver":
             p.local_solver = LOCAL_SOLVER[val] if isinstance(val, str) else val
+        elif key == "inner_launch":
+            p.inner_launch = INNER_LAUNCH[val] if isinstance(val, str) else val
         else:
             setattr(p, key, val)
     h = ctypes.c_void_p()

@@ -114,6 +114,11 @@ struct dd_handle {
   long long nffac = 0;
   // two-level method (coarse_intervals > 0)
   ddh::GlobalCoarse* gc = nullptr;
+  // multi-launch subdomain solves (inner_launch == DD_INNER_MULTI)
+  bool multi = false;
+  ddh::MultiArgs mk{};          // workspaces; per call the caller's vectors are filled in
+  int* active_h = nullptr;      // pinned
+
   std::vector<void*> allocs;
 
   template <typename T>
@@ -140,6 +145,8 @@ struct dd_handle {
     graph_exec = nullptr;
     graph = nullptr;
     cap_stream = nullptr;
+    if (active_h) (void)hipHostFree(active_h);
+    active_h = nullptr;
     if (done_h) (void)hipHostFree(done_h);
     if (res_h) (void)hipHostFree(res_h);
     done_h = nullptr;
@@ -205,6 +212,16 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
     return fail(DD_EINVAL, "coarse_intervals must be 0 (one-level) or in [2, N] with at most 1025 intervals");
   if (p->use_graph && (p->graph_steps < 1 || p->graph_steps > kMaxGraphSteps))
     return fail(DD_EINVAL, "graph_steps must be in [1, 64]");
+  if (p->inner_launch != DD_INNER_FUSED && p->inner_launch != DD_INNER_MULTI)
+    return fail(DD_EINVAL, "inner_launch must be DD_INNER_FUSED or DD_INNER_MULTI");
+  if (p->inner_launch == DD_INNER_MULTI) {
+    if (p->local_solver != DD_LOCAL_DEFLATED_GMRES)
+      return fail(DD_EINVAL, "the multi-launch form runs deflated-GMRES local solves");
+    if (p->inner_precision != 64) return fail(DD_EINVAL, "the multi-launch form needs inner_precision 64");
+    if (p->nrhs != 1) return fail(DD_EINVAL, "the multi-launch form needs nrhs 1");
+    if (p->use_graph) return fail(DD_EINVAL, "the multi-launch form needs use_graph 0");
+    if (p->inner_maxit > ddh::kMultiMaxIt) return fail(DD_EINVAL, "the multi-launch form needs inner_maxit <= 256");
+  }
   auto cuts = [&](const int* c, int parts, std::vector<int>& out) -> dd_status {
     out.resize(parts + 1);
     for (int q = 0; q <= parts; ++q) out[q] = c ? c[q] : (int)(((long long)q * n) / parts);
@@ -231,6 +248,7 @@ dd_status validate_and_plan(const dd_params* p, dd_handle* h) {
   const bool imp = p->local_bc == DD_LOCAL_IMPEDANCE;
   h->subs_h.clear();
   h->direct = p->local_solver == DD_LOCAL_DIRECT;
+  h->multi = p->inner_launch == DD_INNER_MULTI;
   h->foff_h.clear();
   long long off = 0, coff = 0, goff = 0, foff = 0;
   for (int qy = 0; qy < p->py; ++qy) {
@@ -393,6 +411,15 @@ dd_status run_inner(dd_handle* h, const cplx<double>* r, long long rstride, cplx
     a.r = r; a.z = z; a.done = done; a.rstride = rstride; a.zstride = zstride;
     a.jdev = jdev; a.rslot = rslot; a.zslot = zslot; a.zadd = zadd;
     DD_HIP(ddh::launch_direct_solve(a, st));
+    return DD_OK;
+  }
+  if (h->multi) {
+    ddh::MultiArgs a = h->mk;
+    a.r = r; a.z = z; a.zadd = zadd; a.done = done;
+    a.jdev = jdev; a.rslot = rslot; a.zslot = zslot;
+    a.U = nullptr;
+    (void)rstride; (void)zstride;   // one right-hand side
+    DD_HIP(ddh::run_multi_inner(a, h->active_h, st));
     return DD_OK;
   }
   const float* gt = h->net ? h->net->y : nullptr;   // (exact solves take no guess)
@@ -563,6 +590,47 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     o.restart = m;
     DD_HIP(hipHostMalloc((void**)&h->done_h, h->nrhs * sizeof(int), hipHostMallocDefault));
     DD_HIP(hipHostMalloc((void**)&h->res_h, h->nrhs * sizeof(double), hipHostMallocDefault));
+    if (h->multi) {
+      ddh::MultiArgs& a = h->mk;
+      const size_t nf = (size_t)h->nfine, nc = (size_t)h->ncoarse, ns = (size_t)h->nsub, m = (size_t)h->maxit;
+      a.subs = h->subs;
+      a.cs = h->cs;
+      a.local_bc = h->p.local_bc;
+      a.fac = h->fac;
+      a.Ec = h->Ec;
+      a.F = (cplx<double>*)h->F;
+      a.W = (cplx<double>*)h->W;
+      a.X = (cplx<double>*)h->X;
+      a.V = (cplx<double>*)h->V;
+      a.R = h->R;
+      a.iters = h->iters;
+      a.flags = h->flags;
+      a.counters = h->counters;
+      DD_TRY(h->alloc(&a.T, nf));
+      DD_TRY(h->alloc(&a.Bv, nf));
+      DD_TRY(h->alloc(&a.Zc, nf));
+      DD_TRY(h->alloc(&a.t, nc));
+      DD_TRY(h->alloc(&a.Cv, nc));
+      DD_TRY(h->alloc(&a.Yk, (m + 2) * nc));
+      DD_TRY(h->alloc(&a.H, ns * (m + 1)));
+      DD_TRY(h->alloc(&a.g, ns * (m + 1)));
+      DD_TRY(h->alloc(&a.csn, ns * m));
+      DD_TRY(h->alloc(&a.snn, ns * m));
+      DD_TRY(h->alloc(&a.fnorm, ns));
+      DD_TRY(h->alloc(&a.ref, ns));
+      DD_TRY(h->alloc(&a.wn, ns));
+      DD_TRY(h->alloc(&a.active, ns));
+      DD_TRY(h->alloc(&a.notconv, ns));
+      DD_TRY(h->alloc(&a.nactive, 1));
+      a.nfine = h->nfine;
+      a.ncoarse = h->ncoarse;
+      a.nsub = h->nsub;
+      a.maxit = h->maxit;
+      a.max_nj = h->max_nj;
+      a.max_nc = h->max_nc;
+      a.tol = h->p.inner_tol;
+      DD_HIP(hipHostMalloc((void**)&h->active_h, sizeof(int), hipHostMallocDefault));
+    }
     return DD_OK;
   };
   s = body();
@@ -586,6 +654,7 @@ dd_status dd_set_graph(dd_handle* h, int use_graph) {
   DD_TRY(check_handle(h));
   if (use_graph && (h->p.graph_steps < 1 || h->p.graph_steps > kMaxGraphSteps))
     return fail(DD_EINVAL, "graph_steps must be in [1, 64]");
+  if (use_graph && h->multi) return fail(DD_EINVAL, "the multi-launch form cannot be graph-captured");
   h->p.use_graph = use_graph ? 1 : 0;
   return DD_OK;
 }
@@ -852,6 +921,7 @@ static void invalidate_graph(dd_handle* h) {
 
 extern "C" dd_status dd_autotune(dd_handle* h, const char* cache_path, void* stream, char* report, int report_len) {
   DD_TRY(check_handle(h));
+  if (h->multi) return fail(DD_EINVAL, "the multi-launch form has no launch configuration to tune");
   hipStream_t st = (hipStream_t)stream;
   const std::string sig = tune_signature(h);
   std::string rep;
@@ -1055,6 +1125,7 @@ dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void
                             void* stream) {
   DD_TRY(check_handle(h));
   if (!f || !u) return fail(DD_EINVAL, "null vector");
+  if (h->multi && guess) return fail(DD_EINVAL, "the multi-launch form takes no initial guess");
   hipStream_t st = (hipStream_t)stream;
   const size_t bytes = (size_t)h->nfine * h->nrhs * (h->prec == 32 ? 8 : 16);
   DD_HIP(hipMemcpyAsync(h->F, f, bytes, hipMemcpyDeviceToDevice, st));
@@ -1063,6 +1134,10 @@ dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void
     a.F = (const cplx<double>*)h->F;
     a.U = (cplx<double>*)u;
     DD_HIP(ddh::launch_direct_solve(a, st));
+  } else if (h->multi) {
+    ddh::MultiArgs a = h->mk;
+    a.U = (cplx<double>*)u;
+    DD_HIP(ddh::run_multi_inner(a, h->active_h, st));
   } else if (h->prec == 32) {
     auto a = inner_args<float>(h);
     a.guess = (const cplx<float>*)guess;
@@ -1085,6 +1160,7 @@ dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void
 
 dd_status dd_set_guess(dd_handle* h, dd_net* net) {
   DD_TRY(check_handle(h));
+  if (net && h->multi) return fail(DD_EINVAL, "the multi-launch form takes no guess network");
   if (net) {
     for (const SubDesc& d : h->subs_h)
       if (d.nx > net->T || d.ny > net->T)

@@ -743,6 +743,13 @@ hipError_t configure_inner(int max_nj, int max_nc, int maxit) {
   if (e == hipSuccess && lds2 > 65536)
     e = hipFuncSetAttribute((const void*)deflated_apply_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds2);
+  const size_t lds3 = align16(kClasses * kStencilPts * sizeof(cplx<T>)) + (size_t)max_nj * sizeof(cplx<T>);
+  if (e == hipSuccess && lds3 > 65536)
+    e = hipFuncSetAttribute((const void*)local_apply_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds3);
+  const size_t lds4 = 5 * (size_t)max_nc * sizeof(cplx<double>);
+  if (e == hipSuccess && lds4 > 65536)
+    e = hipFuncSetAttribute((const void*)coarse_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds4);
   return e;
 }
 

@@ -86,6 +86,57 @@ template <typename T>
 hipError_t launch_scatter(const SubDesc* subs, int nsub, Consts cs, const cplx<T>* u, cplx<double>* z,
                           long long nfine, long long ndof, int nrhs, hipStream_t st);
 
+// ---- plain multi-kernel subdomain solves (FP64, one right-hand side) -------------------
+// The subdomain GMRES of the batched kernel as a sequence of batched launches per stage,
+// iterated from the host (one synchronisation per inner iteration, no graph).
+constexpr int kMultiMaxIt = 256;   // largest inner_maxit of this path
+struct MultiArgs {
+  const SubDesc* subs;
+  Consts cs;
+  int local_bc;
+  const cplx<double>* fac;       // coarse block-LU factors
+  const cplx<double>* Ec;        // coarse 9-point coefficients
+  const cplx<double>* r;         // global right-hand side [ndof], or null: use F (unscaled, scaled in place)
+  cplx<double>* z;               // global output (owned nodes), or null
+  const cplx<double>* zadd;      // added to z at the owned nodes, or null
+  const int* jdev;               // if set: r and z are advanced by (*jdev) * rslot / zslot
+  long long rslot, zslot;
+  const int* done;               // skip the solve when *done is set, or null
+  cplx<double>* U;               // packed solutions (all tile nodes), or null
+  // packed fine work vectors [nfine]
+  cplx<double>* F;               // scaled local right-hand sides
+  cplx<double>* W;               // deflated operator output / Arnoldi vector
+  cplx<double>* T;               // stencil input
+  cplx<double>* Bv;              // B v
+  cplx<double>* X;               // x = V y
+  cplx<double>* Zc;              // Z c of the recovery
+  cplx<double>* V;               // Krylov bases: solve s at V + off_s (maxit + 1)
+  // packed coarse vectors [ncoarse]
+  cplx<double>* t;               // Z^T v
+  cplx<double>* Yk;              // [maxit + 2][ncoarse]: slot 0 E^{-1} Z^T f, slot 2 + i E^{-1} Z^T B v_i
+  cplx<double>* Cv;              // coarse vector of the recovery
+  // per solve
+  cplx<double>* H;               // Hessenberg column [nsub][maxit + 1]
+  cplx<double>* g;               // rotated right-hand side [nsub][maxit + 1]
+  double* csn;                   // rotation cosines [nsub][maxit]
+  cplx<double>* snn;             // rotation sines [nsub][maxit]
+  cplx<double>* R;               // upper-triangular factor [nsub][maxit][maxit] (column k at k maxit)
+  double* fnorm;                 // ||R_j r||
+  double* ref;                   // ||P f|| of the scaled problem
+  double* wn;                    // ||P B v_k|| before orthogonalisation (breakdown scale)
+  int* active;                   // 1 while the solve iterates
+  int* notconv;                  // 1 when it stopped at maxit without converging
+  int* nactive;                  // [1] active solves
+  int* iters;                    // [nsub] inner iterations
+  int* flags;                    // [nsub] bit1 not converged
+  unsigned long long* counters;  // as InnerArgs
+  long long nfine, ncoarse;
+  int nsub, maxit, max_nj, max_nc;
+  double tol;
+};
+// active_host: pinned host int the loop reads the active count into.
+hipError_t run_multi_inner(const MultiArgs& a, int* active_host, hipStream_t st);
+
 // ---- exact subdomain solves (FP64 block LU of the local matrices) ---------------------
 struct DirectArgs {
   const SubDesc* subs;

@@ -26,7 +26,7 @@ def test_default_params():
     assert p.k == 20.0 and p.ppwl == 10.0 and p.px == 2 and p.py == 2
     assert p.overlap == 1 and p.local_bc == 0 and p.deflation == 0
     assert p.inner_precision == 64 and p.inner_tol == 1e-2 and p.outer_tol == 1e-6
-    assert p.nrhs == 1 and p.outer_restart == 0 and p.coarse_intervals == 0
+    assert p.nrhs == 1 and p.outer_restart == 0 and p.coarse_intervals == 0 and p.inner_launch == 0
 
 
 @pytest.mark.parametrize("kw,needle", [
@@ -47,6 +47,12 @@ def test_default_params():
     (dict(n_intervals=32, coarse_intervals=33), "coarse_intervals"),
     (dict(n_intervals=2400, px=8, py=8, coarse_intervals=1100), "coarse_intervals"),
     (dict(coarse_intervals=-3), "coarse_intervals"),
+    (dict(inner_launch=2), "inner_launch must be"),
+    (dict(inner_launch="multi", use_graph=0, inner_precision=32), "multi-launch form needs inner_precision 64"),
+    (dict(inner_launch="multi", use_graph=0, nrhs=2), "multi-launch form needs nrhs 1"),
+    (dict(inner_launch="multi"), "multi-launch form needs use_graph 0"),
+    (dict(inner_launch="multi", use_graph=0, inner_maxit=300), "inner_maxit <= 256"),
+    (dict(inner_launch="multi", use_graph=0, local_solver="direct"), "deflated-GMRES local solves"),
 ])
 def test_invalid_parameters_rejected_on_host(kw, needle):
     st, msg = binding.setup_status(**kw)
