@@ -497,7 +497,7 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     DD_TRY(h->alloc(&h->pivmin, h->nsub));
     DD_HIP(ddh::launch_assemble_coarse(h->subs, h->nsub, h->cs, h->p.local_bc, h->Ec, st));
     if (h->p.deflation == DD_DEFLATION_LINEAR)
-      DD_HIP(ddh::launch_factor_coarse(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
+      DD_HIP(ddh::launch_factor_coarse_twisted(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
     else
       DD_HIP(ddh::launch_factor_coarse_paired(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
     h->pivmin_h.resize(h->nsub);

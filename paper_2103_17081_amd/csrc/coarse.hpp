@@ -1,21 +1,34 @@
 // Coarse deflation operator E = Z^T B Z (Sec. 2, eq. 4) for linear interpolation
-// Z = Z^y kron Z^x (eq. 5), and its FP64 block LU.
+// Z = Z^y kron Z^x (eq. 5), and its FP64 block factorisations.
 //
 // With coarse nodes ordered x fastest, E couples a coarse node only to its 3 x 3
 // coarse neighbours, so E is block tridiagonal in the coarse rows: diagonal blocks
 // D_i, sub-diagonal L_i (row i to row i-1), super-diagonal U_i (row i to row i+1),
-// each an mx x mx tridiagonal matrix.  Block LU without block pivoting:
-//     S_0 = D_0,  G_i = S_i^{-1},  H_i = G_i U_i,  S_{i+1} = D_{i+1} - L_{i+1} H_i.
-// Solve E y = t:  a_0 = G_0 t_0,  a_i = G_i (t_i - L_i a_{i-1});
-//                 y_{my-1} = a_{my-1},  y_i = a_i - H_i y_{i+1}.
-// Each S_i is inverted by Gauss-Jordan elimination with partial pivoting.  The
-// solve is then 2 my - 1 dense mx x mx products instead of the n_c-step scalar
-// recurrences of a banded triangular solve; it streams the same number of bytes.
+// each an mx x mx tridiagonal matrix.  E is complex symmetric (B is), so U_i = L_{i+1}^T;
+// the factorisation and the solve both take U_i from the stored L_{i+1}, which keeps the
+// factored matrix exactly symmetric whatever the rounding of the assembly.
 //
-// Storage per subdomain at SubDesc::goff (complex<double>): the my blocks G_i, then
-// the my-1 blocks H_i, each mx*mx row-major (element (r, c) at r*mx + c).
-// E itself is kept as nine coefficients per coarse node, offset index
-// o = 3*(dy+1) + (dx+1) for the neighbour (cx+dx, cy+dy).
+// Twisted block factorisation (elimination from both ends towards the middle row
+// p = (my - 1) / 2), without block pivoting:
+//   top,    i < p:  G_i = (D_i - L_i H_{i-1})^{-1},   H_i = G_i U_i;
+//   bottom, i > p:  K_i = (D_i - U_i J_{i+1})^{-1},   J_i = K_i L_i;
+//   middle:         M   = (D_p - L_p H_{p-1} - U_p J_{p+1})^{-1}.
+// Solve E y = t:
+//   a_i = G_i (t_i - L_i a_{i-1}) for i < p  and  b_i = K_i (t_i - U_i b_{i+1}) for i > p,
+//   both sweeps side by side;  y_p = M (t_p - L_p a_{p-1} - U_p b_{p+1});
+//   y_i = a_i - H_i y_{i+1} (i < p)  and  y_i = b_i - J_i y_{i-1} (i > p), side by side.
+// That is my sequential dense mx x mx products (against 2 my - 1 for the one-ended block
+// LU), with the same 2 my - 1 stored blocks and the same bytes streamed.  Each inverse
+// is formed by Gauss-Jordan elimination with partial pivoting.
+//
+// Storage per subdomain at SubDesc::goff (complex<double>), mx*mx row-major blocks
+// (element (r, c) at r*mx + c): G_0..G_{p-1}, H_0..H_{p-1}, K_{p+1}..K_{my-1},
+// J_{p+1}..J_{my-1}, M.  E itself is kept as nine coefficients per coarse node, offset
+// index o = 3*(dy+1) + (dx+1) for the neighbour (cx+dx, cy+dy).
+//
+// The one-ended block LU (S_0 = D_0, G_i = S_i^{-1}, H_i = G_i U_i,
+// S_{i+1} = D_{i+1} - L_{i+1} H_i; blocks G_0..G_{my-1}, H_0..H_{my-2}) is kept for the
+// exact local solves, which factor the local matrices through the same kernel.
 #pragma once
 
 #include "common.hpp"
@@ -28,6 +41,14 @@ constexpr int kCoarseBatch = 8;     // block steps whose factor entries are load
 __host__ __device__ __forceinline__ long long coarse_factor_size(int mx, int my) {
   return (long long)(2 * my - 1) * mx * mx;
 }
+
+// Twisted factorisation: middle row and block offsets (in units of mx*mx blocks).
+__host__ __device__ __forceinline__ int twist_row(int my) { return (my - 1) / 2; }
+__host__ __device__ __forceinline__ int tw_G(int i) { return i; }
+__host__ __device__ __forceinline__ int tw_H(int p, int i) { return p + i; }
+__host__ __device__ __forceinline__ int tw_K(int p, int i) { return p + i - 1; }
+__host__ __device__ __forceinline__ int tw_J(int my, int i) { return my + i - 2; }
+__host__ __device__ __forceinline__ int tw_M(int my) { return 2 * my - 2; }
 
 // Bezier deflation couples coarse nodes up to two rows apart, so its E is taken as
 // block tridiagonal over pairs of coarse rows (block size bmx = 2 mx, bmy block rows; an
@@ -153,14 +174,6 @@ __device__ __forceinline__ void block_solve_ring(int mx, int my, const cplx<doub
   }
 }
 
-// Coarse solve through the ring with E's lower couplings staged in LDS (lc).
-template <int L, int Q>
-__device__ __forceinline__ void coarse_solve_ring(const SubDesc& d, const cplx<double>* __restrict__ F,
-                                                  const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
-  auto lower = [lc, mx = d.mx](int i, int c, int e) { return lc[3 * (i * mx + c) + e]; };
-  block_solve_ring<L, Q, kCoarseBatch>(d.mx, d.my, F, lower, t, a);
-}
-
 // General path for any mx <= kMaxMx: no prefetch, shuffle reductions over groups of
 // L lanes (lower couplings as in block_solve_ring).
 template <int NT, typename Lower>
@@ -205,11 +218,195 @@ __device__ __forceinline__ void block_solve_plain(int mx, int my, const cplx<dou
   }
 }
 
-template <int NT>
-__device__ __forceinline__ void coarse_solve_plain(const SubDesc& d, const cplx<double>* __restrict__ F,
+// ---- twisted solve of E (linear deflation; layout above) ----------------------------
+// The workgroup is split into two halves of Half threads: half 0 runs the top sweep
+// (and the middle row), half 1 the bottom sweep.  Step s of the solve:
+//   s < nf = my - 1 - p:  a_s (top, if s < p) and b_{my-1-s} (bottom);
+//   s = nf:               the coupled middle right-hand side, then y_p;
+//   s > nf:               y_{p-1-(s-nf-1)} (top) and y_{p+1+(s-nf-1)} (bottom).
+// a, b and y share the LDS array `a` (row i at a + i mx); t is used as scratch.
+// lower(i, c, e) = lc[3 (i mx + c) + e]: coupling of unknown c of row i to unknown c+e-1
+// of row i-1; the upper coupling of unknown c of row i-1 to c+e-1 of row i is
+// lower(i, c+e-1, 2-e).
+
+// Factor block (mx*mx units) half h reads at step s, or -1.
+__device__ __forceinline__ int tw_step_block(int h, int s, int p, int my) {
+  const int nf = my - 1 - p;
+  if (s < nf) return h == 0 ? (s < p ? tw_G(s) : -1) : tw_K(p, my - 1 - s);
+  if (s == nf) return h == 0 ? tw_M(my) : -1;
+  const int b = s - nf - 1;
+  if (h == 0) return p - 1 - b >= 0 ? tw_H(p, p - 1 - b) : -1;
+  return p + 1 + b <= my - 1 ? tw_J(my, p + 1 + b) : -1;
+}
+
+// t_{i+1} -= L_{i+1} a_i (top) for unknown c.
+__device__ __forceinline__ void tw_couple_down(int mx, const cplx<double>* lc, int i, int c, cplx<double>* t,
+                                               const cplx<double>* a) {
+  const cplx<double>* lo = lc + 3 * ((i + 1) * mx + c);
+  const cplx<double>* ap = a + i * mx + c;
+  cplx<double> v = t[(i + 1) * mx + c] - lo[1] * ap[0];
+  if (c > 0) v = v - lo[0] * ap[-1];
+  if (c < mx - 1) v = v - lo[2] * ap[1];
+  t[(i + 1) * mx + c] = v;
+}
+
+// t_{i-1} -= U_{i-1} b_i (bottom) for unknown c, U_{i-1} read as L_i^T.
+__device__ __forceinline__ void tw_couple_up(int mx, const cplx<double>* lc, int i, int c, cplx<double>* t,
+                                             const cplx<double>* a) {
+  const cplx<double>* lo = lc + 3 * (i * mx + c);
+  const cplx<double>* bp = a + i * mx + c;
+  cplx<double> v = t[(i - 1) * mx + c] - lo[1] * bp[0];
+  if (c > 0) v = v - lo[-3 + 2] * bp[-1];
+  if (c < mx - 1) v = v - lo[3 + 0] * bp[1];
+  t[(i - 1) * mx + c] = v;
+}
+
+// t_p -= L_p a_{p-1} + U_p b_{p+1} for unknown c.
+__device__ __forceinline__ void tw_couple_middle(int mx, int my, int p, const cplx<double>* lc, int c,
+                                                 cplx<double>* t, const cplx<double>* a) {
+  if (p > 0) tw_couple_down(mx, lc, p - 1, c, t, a);
+  if (p < my - 1) tw_couple_up(mx, lc, p + 1, c, t, a);
+}
+
+// Factor blocks of Depth consecutive steps are loaded together into registers (clamped
+// indices, straight-line code) before those steps run.  Lane l of row group r of a half
+// owns columns l + q L, q < Q (mx <= L Q, rows Half / L >= mx).
+template <int L, int Q, int Depth, int Half>
+__device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<double>* __restrict__ F,
                                                    const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
-  auto lower = [lc, mx = d.mx](int i, int c, int e) { return lc[3 * (i * mx + c) + e]; };
-  block_solve_plain<NT>(d.mx, d.my, F, lower, t, a);
+  const int mm = mx * mx, p = twist_row(my), nf = my - 1 - p, nsteps = 2 * nf + 1;
+  const int h = threadIdx.x / Half, ht = threadIdx.x % Half;
+  const int r = ht / L, l = ht % L;
+  const bool active = r < mx;
+  int col[Q], eoff[Q];
+  bool ok[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    col[q] = l + q * L;
+    ok[q] = active && col[q] < mx;
+    eoff[q] = ok[q] ? r * mx + col[q] : 0;
+  }
+  cplx<double> ring[Depth][Q];
+  for (int s0 = 0; s0 < nsteps; s0 += Depth) {
+#pragma unroll
+    for (int u = 0; u < Depth; ++u) {
+      const int blk = max(tw_step_block(h, s0 + u, p, my), 0);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) ring[u][q] = F[(size_t)blk * mm + eoff[q]];
+    }
+#pragma unroll
+    for (int u = 0; u < Depth; ++u) {
+      const int s = s0 + u;
+      if (s >= nsteps) break;
+      if (s < nf) {
+        // a_s = G_s t_s (top, s < p), b_i = K_i t_i (bottom, i = my-1-s)
+        const int i = h == 0 ? s : my - 1 - s;
+        const bool on = h == 1 || s < p;
+        cplx<double> acc = czero<double>();
+        if (on) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+            if (ok[q]) acc = cfma(ring[u][q], t[i * mx + col[q]], acc);
+        }
+        acc.re = row_sum<L>(acc.re);
+        acc.im = row_sum<L>(acc.im);
+        if (on && active && l == 0) a[i * mx + r] = acc;
+        lds_barrier();
+        if (ht < mx) {
+          if (h == 0) {
+            if (s + 1 < p) tw_couple_down(mx, lc, s, ht, t, a);
+          } else {
+            if (i - 1 > p) tw_couple_up(mx, lc, i, ht, t, a);
+          }
+        }
+        lds_barrier();
+      } else if (s == nf) {
+        if (h == 0 && ht < mx) tw_couple_middle(mx, my, p, lc, ht, t, a);
+        lds_barrier();
+        cplx<double> acc = czero<double>();
+        if (h == 0) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+            if (ok[q]) acc = cfma(ring[u][q], t[p * mx + col[q]], acc);
+        }
+        acc.re = row_sum<L>(acc.re);
+        acc.im = row_sum<L>(acc.im);
+        if (h == 0 && active && l == 0) a[p * mx + r] = acc;
+        lds_barrier();
+      } else {
+        // y_i = a_i - H_i y_{i+1} (top), y_i = b_i - J_i y_{i-1} (bottom)
+        const int b = s - nf - 1;
+        const int i = h == 0 ? p - 1 - b : p + 1 + b;
+        const bool on = h == 0 ? i >= 0 : i <= my - 1;
+        const int src = h == 0 ? i + 1 : i - 1;
+        cplx<double> acc = czero<double>();
+        if (on) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+            if (ok[q]) acc = cfma(ring[u][q], a[src * mx + col[q]], acc);
+        }
+        acc.re = row_sum<L>(acc.re);
+        acc.im = row_sum<L>(acc.im);
+        if (on && active && l == 0) a[i * mx + r] = a[i * mx + r] - acc;
+        lds_barrier();
+      }
+    }
+  }
+}
+
+// Same steps for any mx <= kMaxMx: factor entries read as they are used, shuffle
+// reductions over groups of L = coarse_group_lanes<Half>(mx) lanes.
+template <int Half>
+__device__ __forceinline__ void twisted_solve_plain(int mx, int my, const cplx<double>* __restrict__ F,
+                                                    const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
+  const int mm = mx * mx, p = twist_row(my), nf = my - 1 - p, nsteps = 2 * nf + 1;
+  const int L = coarse_group_lanes<Half>(mx);
+  const int h = threadIdx.x / Half, ht = threadIdx.x % Half;
+  const int r = ht / L, l = ht % L;
+  const bool active = r < mx;
+  auto gsum = [&](cplx<double> v) {
+    for (int o = L >> 1; o > 0; o >>= 1) {
+      v.re += __shfl_xor(v.re, o, kWave);
+      v.im += __shfl_xor(v.im, o, kWave);
+    }
+    return v;
+  };
+  auto product = [&](int blk, const cplx<double>* x) {
+    cplx<double> acc = czero<double>();
+    if (active)
+      for (int c = l; c < mx; c += L) acc = cfma(F[(size_t)blk * mm + r * mx + c], x[c], acc);
+    return gsum(acc);
+  };
+  for (int s = 0; s < nsteps; ++s) {
+    const int blk = tw_step_block(h, s, p, my);
+    if (s < nf) {
+      const int i = h == 0 ? s : my - 1 - s;
+      const cplx<double> acc = product(max(blk, 0), t + i * mx);
+      if (blk >= 0 && active && l == 0) a[i * mx + r] = acc;
+      lds_barrier();
+      if (ht < mx) {
+        if (h == 0) {
+          if (s + 1 < p) tw_couple_down(mx, lc, s, ht, t, a);
+        } else {
+          if (i - 1 > p) tw_couple_up(mx, lc, i, ht, t, a);
+        }
+      }
+      lds_barrier();
+    } else if (s == nf) {
+      if (h == 0 && ht < mx) tw_couple_middle(mx, my, p, lc, ht, t, a);
+      lds_barrier();
+      const cplx<double> acc = product(tw_M(my), t + p * mx);
+      if (h == 0 && active && l == 0) a[p * mx + r] = acc;
+      lds_barrier();
+    } else {
+      const int b = s - nf - 1;
+      const int i = h == 0 ? p - 1 - b : p + 1 + b;
+      const int src = h == 0 ? i + 1 : i - 1;
+      const cplx<double> acc = blk >= 0 ? product(blk, a + src * mx) : czero<double>();
+      if (blk >= 0 && active && l == 0) a[i * mx + r] = a[i * mx + r] - acc;
+      lds_barrier();
+    }
+  }
 }
 
 // Paired-row (Bezier) block solve with dense lower couplings; shuffle reductions over
@@ -275,17 +472,13 @@ __device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double
     detail::coarse_solve_paired<NT>(d, F, t, a);
     return;
   }
-  const int L = coarse_group_lanes<NT>(d.mx);
-  const int Q = (d.mx + L - 1) / L;
-  // one ring shape per workgroup size (each instantiation costs registers in every
-  // kernel that contains it): 512 threads cover mx <= 32 with 16 lanes per row, 256
-  // threads with 8
-  if constexpr (NT >= 512) {
-    if (L == 16 && Q <= 2) detail::coarse_solve_ring<16, 2>(d, F, lc, t, a);
-    else detail::coarse_solve_plain<NT>(d, F, lc, t, a);
+  // the two halves run the two sweeps; rings of 4 steps: 512 threads give 8 lanes per
+  // block row (mx <= 32), 256 threads 4
+  if (d.mx <= 32) {
+    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 4, NT / 2>(d.mx, d.my, F, lc, t, a);
+    else detail::twisted_solve_ring<4, 8, 4, NT / 2>(d.mx, d.my, F, lc, t, a);
   } else {
-    if (L == 8 && Q <= 4) detail::coarse_solve_ring<8, 4>(d, F, lc, t, a);
-    else detail::coarse_solve_plain<NT>(d, F, lc, t, a);
+    detail::twisted_solve_plain<NT / 2>(d.mx, d.my, F, lc, t, a);
   }
 }
 

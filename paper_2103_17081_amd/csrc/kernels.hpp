@@ -10,6 +10,10 @@ hipError_t launch_assemble_coarse(const SubDesc* subs, int nsub, Consts cs, int 
                                   hipStream_t st);
 hipError_t launch_factor_coarse(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
                                 double* pivmin, hipStream_t st);
+// Twisted block factorisation of E (linear deflation); the one-ended block LU
+// (launch_factor_coarse) serves the exact local solves.
+hipError_t launch_factor_coarse_twisted(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
+                                        double* pivmin, hipStream_t st);
 hipError_t launch_factor_coarse_paired(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
                                        double* pivmin, hipStream_t st);
 

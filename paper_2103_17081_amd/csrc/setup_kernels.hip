@@ -152,6 +152,98 @@ __global__ void __launch_bounds__(kBlock) factor_coarse_kernel(const SubDesc* __
   if (tid == 0) pivmin[blockIdx.x] = minp;
 }
 
+// Twisted block factorisation of E (linear deflation; layout and relations in
+// coarse.hpp).  D_i from the stored own-row couplings, L_i from the stored lower
+// couplings, U_i = L_{i+1}^T.
+__global__ void __launch_bounds__(kBlock) factor_coarse_twisted_kernel(const SubDesc* __restrict__ subs,
+                                                                        const cplx<double>* __restrict__ Ec,
+                                                                        cplx<double>* __restrict__ fac,
+                                                                        double* __restrict__ pivmin) {
+  const SubDesc d = subs[blockIdx.x];
+  __shared__ int perm[kMaxMx];
+  __shared__ cplx<double> colp[kMaxMx];
+  __shared__ double pivabs;
+  const int mx = d.mx, my = d.my, mm = mx * mx, tid = threadIdx.x, p = twist_row(my);
+  const cplx<double>* ec = Ec + d.coff * 9;
+  cplx<double>* F = fac + d.goff;
+  // D_i(r, c), L_i(r, c) (unknown r of row i to unknown c of row i-1), U_i(r, c) = L_{i+1}(c, r)
+  auto Dv = [&](int i, int r, int c) {
+    return (c - r >= -1 && c - r <= 1) ? ec[(size_t)(i * mx + r) * 9 + 4 + (c - r)] : czero<double>();
+  };
+  auto Lv = [&](int i, int r, int c) {
+    return (c - r >= -1 && c - r <= 1) ? ec[(size_t)(i * mx + r) * 9 + 1 + (c - r)] : czero<double>();
+  };
+  auto Uv = [&](int i, int r, int c) { return Lv(i + 1, c, r); };
+  auto blk = [&](int b) { return F + (size_t)b * mm; };
+  double minp = 1e300;
+  // top: G_i = (D_i - L_i H_{i-1})^{-1}, H_i = G_i U_i
+  for (int i = 0; i < p; ++i) {
+    cplx<double>* G = blk(tw_G(i));
+    for (int e = tid; e < mm; e += blockDim.x) {
+      const int r = e / mx, c = e - r * mx;
+      cplx<double> s = Dv(i, r, c);
+      if (i > 0) {
+        const cplx<double>* Hp = blk(tw_H(p, i - 1));
+        for (int rr = max(r - 1, 0); rr <= min(r + 1, mx - 1); ++rr) s = s - Lv(i, r, rr) * Hp[rr * mx + c];
+      }
+      G[e] = s;
+    }
+    __syncthreads();
+    minp = fmin(minp, gauss_jordan_inverse(G, mx, perm, colp, &pivabs));
+    cplx<double>* H = blk(tw_H(p, i));
+    for (int e = tid; e < mm; e += blockDim.x) {
+      const int r = e / mx, c = e - r * mx;
+      cplx<double> s = czero<double>();
+      for (int cc = max(c - 1, 0); cc <= min(c + 1, mx - 1); ++cc) s = s + G[r * mx + cc] * Uv(i, cc, c);
+      H[e] = s;
+    }
+    __syncthreads();
+  }
+  // bottom: K_i = (D_i - U_i J_{i+1})^{-1}, J_i = K_i L_i
+  for (int i = my - 1; i > p; --i) {
+    cplx<double>* K = blk(tw_K(p, i));
+    for (int e = tid; e < mm; e += blockDim.x) {
+      const int r = e / mx, c = e - r * mx;
+      cplx<double> s = Dv(i, r, c);
+      if (i < my - 1) {
+        const cplx<double>* Jn = blk(tw_J(my, i + 1));
+        for (int rr = max(r - 1, 0); rr <= min(r + 1, mx - 1); ++rr) s = s - Uv(i, r, rr) * Jn[rr * mx + c];
+      }
+      K[e] = s;
+    }
+    __syncthreads();
+    minp = fmin(minp, gauss_jordan_inverse(K, mx, perm, colp, &pivabs));
+    cplx<double>* J = blk(tw_J(my, i));
+    for (int e = tid; e < mm; e += blockDim.x) {
+      const int r = e / mx, c = e - r * mx;
+      cplx<double> s = czero<double>();
+      for (int cc = max(c - 1, 0); cc <= min(c + 1, mx - 1); ++cc) s = s + K[r * mx + cc] * Lv(i, cc, c);
+      J[e] = s;
+    }
+    __syncthreads();
+  }
+  // middle: M = (D_p - L_p H_{p-1} - U_p J_{p+1})^{-1}
+  cplx<double>* M = blk(tw_M(my));
+  for (int e = tid; e < mm; e += blockDim.x) {
+    const int r = e / mx, c = e - r * mx;
+    cplx<double> s = Dv(p, r, c);
+    for (int rr = max(r - 1, 0); rr <= min(r + 1, mx - 1); ++rr) {
+      if (p > 0) s = s - Lv(p, r, rr) * blk(tw_H(p, p - 1))[rr * mx + c];
+      if (p < my - 1) s = s - Uv(p, r, rr) * blk(tw_J(my, p + 1))[rr * mx + c];
+    }
+    M[e] = s;
+  }
+  __syncthreads();
+  minp = fmin(minp, gauss_jordan_inverse(M, mx, perm, colp, &pivabs));
+  if (tid == 0) pivmin[blockIdx.x] = minp;
+}
+
+hipError_t launch_factor_coarse_twisted(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
+                                        double* pivmin, hipStream_t st) {
+  hipLaunchKernelGGL(factor_coarse_twisted_kernel, dim3(nsub), dim3(kBlock), 0, st, subs, Ec, fac, pivmin);
+  return hipGetLastError();
+}
+
 // Block LU over pairs of coarse rows (Bezier deflation, see coarse.hpp).  Unknown k of
 // block row I is coarse node (k % mx, 2 I + k / mx); a row beyond my is an identity row.
 __device__ __forceinline__ cplx<double> paired_coef(const SubDesc& d, const cplx<double>* __restrict__ ec, int I,
