@@ -464,12 +464,33 @@ __global__ void __launch_bounds__(256) dcgs2_step_kernel(OuterState st, StepRef 
     __syncthreads();
     if (tid == 0) {
       const double hnext = gamma * alpha;
-      for (int i = 0; i < jc; ++i) {
-        const cplx<double> x0 = lcol[i], x1 = lcol[i + 1];
-        lcol[i] = lcs[i] * x0 + lsn[i] * x1;
-        lcol[i + 1] = lcs[i] * x1 - cplx<double>{lsn[i].re, -lsn[i].im} * x0;
+      // The rotations form a chain through the entry they carry down the column.  That
+      // entry stays in registers, and the inputs of a batch of rotations (entries i + 1 of
+      // the column, c_i, s_i: none depends on the chain, and entry i + 1 is not written
+      // before rotation i + 1) are loaded together ahead of it, so a rotation costs a few
+      // dependent FP64 operations instead of an LDS round trip.
+      constexpr int kBatch = 16;
+      cplx<double> x0 = lcol[0];
+      for (int i0 = 0; i0 < jc; i0 += kBatch) {
+        cplx<double> xb[kBatch], sb[kBatch];
+        double cbt[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          const int i = min(i0 + q, jc - 1);
+          xb[q] = lcol[i + 1];
+          cbt[q] = lcs[i];
+          sb[q] = lsn[i];
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          if (i0 + q < jc) {
+            lcol[i0 + q] = cbt[q] * x0 + sb[q] * xb[q];
+            x0 = cbt[q] * xb[q] - cplx<double>{sb[q].re, -sb[q].im} * x0;
+          }
+        }
       }
-      const cplx<double> av = lcol[jc];
+      lcol[jc] = x0;
+      const cplx<double> av = x0;
       const double aa = sqrt(cabs2(av));
       double c;
       cplx<double> sv, r;
