@@ -398,6 +398,72 @@ __global__ void __launch_bounds__(256) dcgs2_update_kernel(cplx<double>* __restr
   }
 }
 
+// Rotations 0..jc-1 applied to the column lcol[0..jc] by all threads of a 256-thread
+// workgroup.  Rotation i maps (x_i, col_{i+1}) to the rotated entry
+// c_i x_i + s_i col_{i+1} and the carried entry x_{i+1} = c_i col_{i+1} - conj(s_i) x_i,
+// with x_0 = col_0; the rotated column is (entries 0..jc-1, x_jc).  The carried entry
+// obeys the affine recurrence x_{i+1} = a_i + m_i x_i (a_i = c_i col_{i+1},
+// m_i = -conj(s_i), |m_i| <= 1), so each thread composes the maps of a segment of
+// rotations, a scan over the threads composes the segments (shuffles within a wave,
+// the four wave totals through `wmap`), and each thread then replays its segment from
+// its starting value: depth about 2 jc / 256 + 8 instead of jc.
+__device__ __forceinline__ cplx<double> cshfl_up(cplx<double> v, int o) {
+  return cplx<double>{__shfl_up(v.re, o, kWave), __shfl_up(v.im, o, kWave)};
+}
+
+__device__ void rotate_column_scan(cplx<double>* lcol, const double* lcs, const cplx<double>* lsn, int jc,
+                                   cplx<double>* wmap) {
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int seg = (jc + 255) / 256;
+  const int i0 = min(tid * seg, jc), i1 = min(i0 + seg, jc);
+  const cplx<double> one{1.0, 0.0};
+  const cplx<double> xstart = lcol[0];
+  const cplx<double> xend = i1 > i0 ? lcol[i1] : czero<double>();
+  // this segment's map x -> A + M x
+  cplx<double> A = czero<double>(), M = one;
+  for (int i = i0; i < i1; ++i) {
+    const cplx<double> m{-lsn[i].re, lsn[i].im};
+    const cplx<double> a = lcs[i] * (i + 1 < i1 ? lcol[i + 1] : xend);
+    A = a + m * A;
+    M = m * M;
+  }
+  // inclusive scan within the wave: (A, M) <- (A, M) o (maps of the lanes below)
+  for (int o = 1; o < kWave; o <<= 1) {
+    const cplx<double> pA = cshfl_up(A, o), pM = cshfl_up(M, o);
+    if (lane >= o) {
+      A = A + M * pA;
+      M = M * pM;
+    }
+  }
+  cplx<double> eA = cshfl_up(A, 1), eM = cshfl_up(M, 1);   // through the previous lane
+  if (lane == 0) {
+    eA = czero<double>();
+    eM = one;
+  }
+  if (lane == kWave - 1) {
+    wmap[2 * wave] = A;
+    wmap[2 * wave + 1] = M;
+  }
+  __syncthreads();
+  // composition of the earlier waves, then the entry carried into this segment
+  cplx<double> PA = czero<double>(), PM = one;
+  for (int w = 0; w < wave; ++w) {
+    const cplx<double> WA = wmap[2 * w], WM = wmap[2 * w + 1];
+    PA = WA + WM * PA;
+    PM = WM * PM;
+  }
+  cplx<double> x = eA + eM * (PA + PM * xstart);
+  // replay the segment; entry i1 (the next segment's first) was read before the barrier
+  for (int i = i0; i < i1; ++i) {
+    const cplx<double> x1 = i + 1 < i1 ? lcol[i + 1] : xend;
+    const double c = lcs[i];
+    const cplx<double> sv = lsn[i];
+    lcol[i] = c * x + sv * x1;
+    x = c * x1 - cplx<double>{sv.re, -sv.im} * x;
+  }
+  if (i1 == jc && i1 > i0) lcol[jc] = x;
+}
+
 // Delayed CGS2 bookkeeping of step j for every active right-hand side (one workgroup
 // each).  From the pass-1 dots (s = V_j^H u~_j, c = V_j^H w, nu = |u~_j|^2,
 // mu = u~_j^H w, ww = |w|^2):
@@ -431,6 +497,7 @@ __global__ void __launch_bounds__(256) dcgs2_step_kernel(OuterState st, StepRef 
   __shared__ cplx<double> redc[4];
   __shared__ double sh_alpha;
   __shared__ int sh_conv;
+  __shared__ cplx<double> wmap[8];
   const cplx<double>* D = dots + (long long)rhs * dstride;
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   // |s|^2
@@ -462,35 +529,11 @@ __global__ void __launch_bounds__(256) dcgs2_step_kernel(OuterState st, StepRef 
       if (i < jc) { lsn[i] = sn[i]; lcs[i] = cs[i]; }
     }
     __syncthreads();
+    rotate_column_scan(lcol, lcs, lsn, jc, wmap);
+    __syncthreads();
     if (tid == 0) {
       const double hnext = gamma * alpha;
-      // The rotations form a chain through the entry they carry down the column.  That
-      // entry stays in registers, and the inputs of a batch of rotations (entries i + 1 of
-      // the column, c_i, s_i: none depends on the chain, and entry i + 1 is not written
-      // before rotation i + 1) are loaded together ahead of it, so a rotation costs a few
-      // dependent FP64 operations instead of an LDS round trip.
-      constexpr int kBatch = 16;
-      cplx<double> x0 = lcol[0];
-      for (int i0 = 0; i0 < jc; i0 += kBatch) {
-        cplx<double> xb[kBatch], sb[kBatch];
-        double cbt[kBatch];
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-          const int i = min(i0 + q, jc - 1);
-          xb[q] = lcol[i + 1];
-          cbt[q] = lcs[i];
-          sb[q] = lsn[i];
-        }
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-          if (i0 + q < jc) {
-            lcol[i0 + q] = cbt[q] * x0 + sb[q] * xb[q];
-            x0 = cbt[q] * xb[q] - cplx<double>{sb[q].re, -sb[q].im} * x0;
-          }
-        }
-      }
-      lcol[jc] = x0;
-      const cplx<double> av = x0;
+      const cplx<double> av = lcol[jc];
       const double aa = sqrt(cabs2(av));
       double c;
       cplx<double> sv, r;
