@@ -472,10 +472,10 @@ __device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double
     detail::coarse_solve_paired<NT>(d, F, t, a);
     return;
   }
-  // the two halves run the two sweeps; rings of 4 steps: 512 threads give 8 lanes per
-  // block row (mx <= 32), 256 threads 4
+  // the two halves run the two sweeps: 512 threads give 8 lanes per block row (mx <= 32)
+  // and a ring of 8 steps, 256 threads 4 lanes and a ring of 4 (register budget)
   if (d.mx <= 32) {
-    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 4, NT / 2>(d.mx, d.my, F, lc, t, a);
+    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 8, NT / 2>(d.mx, d.my, F, lc, t, a);
     else detail::twisted_solve_ring<4, 8, 4, NT / 2>(d.mx, d.my, F, lc, t, a);
   } else {
     detail::twisted_solve_plain<NT / 2>(d.mx, d.my, F, lc, t, a);
