@@ -77,8 +77,9 @@ typedef struct {
   int use_graph;       /* 1: outer steps replayed from a captured hipGraph (default), 0: launched one by one */
   int graph_steps;     /* outer steps per graph replay; convergence is read back once per replay */
   int local_solver;    /* DD_LOCAL_DEFLATED_GMRES (default): inexact deflated-GMRES subdomain solves;
-                          DD_LOCAL_DIRECT: exact solves with the FP64 block LU of each local matrix
-                          (the direct-solve baseline of Sec. 3, Table 1); needs inner_precision 64,
+                          DD_LOCAL_DIRECT: exact solves with the FP64 twisted block
+                          factorisation of each local matrix (the direct-solve baseline of
+                          Sec. 3, Table 1); needs inner_precision 64,
                           ignores the inner tolerances and the deflation choice */
   int coarse_intervals; /* 0 (default): the one-level preconditioner of eq. 3.  M >= 2: two-level
                           method with a global coarse space, the extension the paper's
@@ -151,7 +152,8 @@ typedef struct {
 void dd_default_params(dd_params* p);
 
 /* Build the mesh, the partition, every E_j = Z_j^T B_j Z_j (Sec. 2, eq. 4) and its
-   FP64 block LU on the device, and allocate all workspaces.  `stream` orders the
+   FP64 block factorisation on the device (twisted for linear deflation, one-ended over
+   paired rows for Bezier), and allocate all workspaces.  `stream` orders the
    set-up work; the call synchronises it.  Errors: DD_EINVAL (bad parameters,
    reported before allocating), DD_ENOMEM, DD_EHIP, DD_ESINGULAR. */
 dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out);
@@ -198,7 +200,7 @@ dd_status dd_layout(const dd_handle* h, int32_t* out);
 
 /* Host copy of the coefficients of E_j per coarse node (complex128, [nc][K]; K = 9 for
    linear deflation, neighbour (cx+dx, cy+dy) at 3(dy+1) + (dx+1); K = 25 for Bezier,
-   neighbour at 5(dy+2) + (dx+2)) and min |pivot| of its block LU. */
+   neighbour at 5(dy+2) + (dx+2)) and min |pivot| of its block factorisation. */
 dd_status dd_coarse_matrix(const dd_handle* h, int j, double* out, double* min_pivot);
 
 /* ---- kernel-level entry points (parity tests, profiling) ------------------------ */
@@ -213,7 +215,7 @@ dd_status dd_op_deflated_apply(dd_handle* h, int precision, const void* v, void*
 dd_status dd_op_restrict(dd_handle* h, const void* v, void* t, void* stream);
 /* v_j = Z_j y_j; complex128 coarse -> fine. */
 dd_status dd_op_prolong(dd_handle* h, const void* y, void* v, void* stream);
-/* y_j = E_j^{-1} t_j with the FP64 block LU; complex128 coarse vectors. */
+/* y_j = E_j^{-1} t_j with the FP64 block factorisation; complex128 coarse vectors. */
 dd_status dd_op_coarse_solve(dd_handle* h, const void* t, void* y, void* stream);
 /* f_j = R_j r (packed, precision 64 or 32) from global r; one right-hand side. */
 dd_status dd_op_gather(dd_handle* h, int precision, const void* r, void* f, void* stream);

@@ -108,7 +108,7 @@ struct dd_handle {
   dd_net* net = nullptr;        // attached guess network (borrowed)
   // exact local solves (local_solver == DD_LOCAL_DIRECT)
   bool direct = false;
-  cplx<double>* ffac = nullptr; // block-LU factors of the local matrices
+  cplx<double>* ffac = nullptr; // twisted block factors of the local matrices
   long long* foff = nullptr;    // [nsub] factor offsets
   std::vector<long long> foff_h;
   long long nffac = 0;
@@ -507,7 +507,7 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
       if (!(h->pivmin_h[j] > 0.0) || !std::isfinite(h->pivmin_h[j]))
         return fail(DD_ESINGULAR, "coarse matrix E_" + std::to_string(j) + " is singular (zero pivot)");
     if (h->direct) {
-      // block LU of every local matrix: its 9-coefficient form, factored by the same
+      // twisted block factorisation of every local matrix: its 9-coefficient form, factored by the same
       // kernel as E through per-subdomain views (block size nx, ny block rows)
       DD_TRY(h->alloc(&h->ffac, (size_t)h->nffac));
       DD_TRY(h->alloc(&h->foff, h->nsub));
@@ -525,7 +525,7 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
       hipError_t e = hipMalloc((void**)&vd, h->nsub * sizeof(SubDesc));
       if (e == hipSuccess) e = hipMemcpy(vd, views.data(), h->nsub * sizeof(SubDesc), hipMemcpyHostToDevice);
       if (e == hipSuccess) e = ddh::launch_fine_coef(h->subs, h->nsub, h->cs, h->p.local_bc, Bc, st);
-      if (e == hipSuccess) e = ddh::launch_factor_coarse(vd, h->nsub, Bc, h->ffac, h->pivmin, st);
+      if (e == hipSuccess) e = ddh::launch_factor_coarse_twisted(vd, h->nsub, Bc, h->ffac, h->pivmin, st);
       if (e == hipSuccess) e = hipMemcpyAsync(h->pivmin_h.data(), h->pivmin, h->nsub * sizeof(double),
                                               hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -26,9 +26,8 @@
 // J_{p+1}..J_{my-1}, M.  E itself is kept as nine coefficients per coarse node, offset
 // index o = 3*(dy+1) + (dx+1) for the neighbour (cx+dx, cy+dy).
 //
-// The one-ended block LU (S_0 = D_0, G_i = S_i^{-1}, H_i = G_i U_i,
-// S_{i+1} = D_{i+1} - L_{i+1} H_i; blocks G_0..G_{my-1}, H_0..H_{my-2}) is kept for the
-// exact local solves, which factor the local matrices through the same kernel.
+// The exact local solves factor the local matrices B_j the same way (block size nx, ny
+// block rows), through the same set-up kernel and solve.
 #pragma once
 
 #include "common.hpp"
@@ -36,7 +35,6 @@
 namespace ddh {
 
 constexpr int kMaxMx = 128;   // largest coarse block (mx) the kernels support
-constexpr int kCoarseBatch = 8;     // block steps whose factor entries are loaded together
 
 __host__ __device__ __forceinline__ long long coarse_factor_size(int mx, int my) {
   return (long long)(2 * my - 1) * mx * mx;
@@ -88,136 +86,6 @@ __device__ __forceinline__ void stage_lower(const SubDesc& d, const cplx<double>
 
 namespace detail {
 
-// Block-tridiagonal solve with inverted diagonal blocks (the factor layout above), for
-// any operator whose lower coupling L_i is tridiagonal: lower(i, c, e) is the coupling
-// of unknown c of block row i to unknown c + e - 1 of block row i - 1 (e = 0, 1, 2).
-// Lane l of group r owns columns c = l + q L (q < Q).  The factor entries of Depth
-// consecutive steps are loaded together, in straight-line code with clamped indices,
-// before those steps run, so memory latency is paid once per batch rather than once per
-// step.  The coupled right-hand side t_i - L_i a_{i-1} is formed once per column
-// (threads 0..mx-1, in place in t) between the block products instead of by every row
-// group.
-template <int L, int Q, int Depth, typename Lower>
-__device__ __forceinline__ void block_solve_ring(int mx, int my, const cplx<double>* __restrict__ F, Lower lower,
-                                                 cplx<double>* t, cplx<double>* a) {
-  const int mm = mx * mx;
-  const int r = threadIdx.x / L, l = threadIdx.x % L;
-  const bool active = r < mx;
-  int col[Q];
-  bool ok[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    col[q] = l + q * L;
-    ok[q] = active && col[q] < mx;
-  }
-  // element offset of this lane's entry q inside a block (clamped to 0 when unused)
-  int eoff[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) eoff[q] = ok[q] ? r * mx + col[q] : 0;
-  cplx<double> ring[Depth][Q];
-  // forward: a_i = G_i (t_i - L_i a_{i-1}), G_i = block i
-  for (int i0 = 0; i0 < my; i0 += Depth) {
-#pragma unroll
-    for (int u = 0; u < Depth; ++u) {
-      const int blk = min(i0 + u, my - 1);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) ring[u][q] = F[(size_t)blk * mm + eoff[q]];
-    }
-#pragma unroll
-    for (int u = 0; u < Depth; ++u) {
-      const int i = i0 + u;
-      if (i < my) {
-        cplx<double> acc = czero<double>();
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-          if (ok[q]) acc = cfma(ring[u][q], t[i * mx + col[q]], acc);
-        acc.re = row_sum<L>(acc.re);
-        acc.im = row_sum<L>(acc.im);
-        if (active && l == 0) a[i * mx + r] = acc;
-        lds_barrier();
-        if (i + 1 < my) {
-          const int c = threadIdx.x;
-          if (c < mx) {
-            const cplx<double>* ap = a + i * mx + c;
-            cplx<double> rhs = t[(i + 1) * mx + c] - lower(i + 1, c, 1) * ap[0];
-            if (c > 0) rhs = rhs - lower(i + 1, c, 0) * ap[-1];
-            if (c < mx - 1) rhs = rhs - lower(i + 1, c, 2) * ap[1];
-            t[(i + 1) * mx + c] = rhs;
-          }
-          lds_barrier();
-        }
-      }
-    }
-  }
-  // backward: y_i = a_i - H_i y_{i+1}, H_i = block my + i, i = my-2 .. 0
-  for (int i0 = my - 2; i0 >= 0; i0 -= Depth) {
-#pragma unroll
-    for (int u = 0; u < Depth; ++u) {
-      const int blk = my + max(i0 - u, 0);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) ring[u][q] = F[(size_t)blk * mm + eoff[q]];
-    }
-#pragma unroll
-    for (int u = 0; u < Depth; ++u) {
-      const int i = i0 - u;
-      if (i >= 0) {
-        cplx<double> acc = czero<double>();
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-          if (ok[q]) acc = cfma(ring[u][q], a[(i + 1) * mx + col[q]], acc);
-        acc.re = row_sum<L>(acc.re);
-        acc.im = row_sum<L>(acc.im);
-        if (active && l == 0) a[i * mx + r] = a[i * mx + r] - acc;
-        lds_barrier();
-      }
-    }
-  }
-}
-
-// General path for any mx <= kMaxMx: no prefetch, shuffle reductions over groups of
-// L lanes (lower couplings as in block_solve_ring).
-template <int NT, typename Lower>
-__device__ __forceinline__ void block_solve_plain(int mx, int my, const cplx<double>* __restrict__ F, Lower lower,
-                                                  cplx<double>* t, cplx<double>* a) {
-  const int mm = mx * mx;
-  const int L = coarse_group_lanes<NT>(mx);
-  const int r = threadIdx.x / L, l = threadIdx.x % L;
-  const bool active = r < mx;
-  auto gsum = [&](cplx<double> v) {
-    for (int o = L >> 1; o > 0; o >>= 1) {
-      v.re += __shfl_xor(v.re, o, kWave);
-      v.im += __shfl_xor(v.im, o, kWave);
-    }
-    return v;
-  };
-  for (int i = 0; i < my; ++i) {
-    cplx<double> acc = czero<double>();
-    if (active) {
-      for (int c = l; c < mx; c += L) {
-        cplx<double> rhs = t[i * mx + c];
-        if (i > 0) {
-          for (int e = 0; e < 3; ++e) {
-            const int cc = c + e - 1;
-            if (cc >= 0 && cc < mx) rhs = rhs - lower(i, c, e) * a[(i - 1) * mx + cc];
-          }
-        }
-        acc = cfma(F[(size_t)i * mm + r * mx + c], rhs, acc);
-      }
-    }
-    acc = gsum(acc);
-    if (active && l == 0) a[i * mx + r] = acc;
-    lds_barrier();
-  }
-  for (int i = my - 2; i >= 0; --i) {
-    cplx<double> acc = czero<double>();
-    if (active)
-      for (int c = l; c < mx; c += L) acc = cfma(F[(size_t)(my + i) * mm + r * mx + c], a[(i + 1) * mx + c], acc);
-    acc = gsum(acc);
-    if (active && l == 0) a[i * mx + r] = a[i * mx + r] - acc;
-    lds_barrier();
-  }
-}
-
 // ---- twisted solve of E (linear deflation; layout above) ----------------------------
 // The workgroup is split into two halves of Half threads: half 0 runs the top sweep
 // (and the middle row), half 1 the bottom sweep.  Step s of the solve:
@@ -225,9 +93,9 @@ __device__ __forceinline__ void block_solve_plain(int mx, int my, const cplx<dou
 //   s = nf:               the coupled middle right-hand side, then y_p;
 //   s > nf:               y_{p-1-(s-nf-1)} (top) and y_{p+1+(s-nf-1)} (bottom).
 // a, b and y share the LDS array `a` (row i at a + i mx); t is used as scratch.
-// lower(i, c, e) = lc[3 (i mx + c) + e]: coupling of unknown c of row i to unknown c+e-1
-// of row i-1; the upper coupling of unknown c of row i-1 to c+e-1 of row i is
-// lower(i, c+e-1, 2-e).
+// lower(i, c, e): coupling of unknown c of row i to unknown c+e-1 of row i-1 (for E, the
+// staged lc[3 (i mx + c) + e]); the upper coupling of unknown c of row i-1 to c+e-1 of
+// row i is lower(i, c+e-1, 2-e).
 
 // Factor block (mx*mx units) half h reads at step s, or -1.
 __device__ __forceinline__ int tw_step_block(int h, int s, int p, int my) {
@@ -240,40 +108,41 @@ __device__ __forceinline__ int tw_step_block(int h, int s, int p, int my) {
 }
 
 // t_{i+1} -= L_{i+1} a_i (top) for unknown c.
-__device__ __forceinline__ void tw_couple_down(int mx, const cplx<double>* lc, int i, int c, cplx<double>* t,
+template <typename Lower>
+__device__ __forceinline__ void tw_couple_down(int mx, Lower lower, int i, int c, cplx<double>* t,
                                                const cplx<double>* a) {
-  const cplx<double>* lo = lc + 3 * ((i + 1) * mx + c);
   const cplx<double>* ap = a + i * mx + c;
-  cplx<double> v = t[(i + 1) * mx + c] - lo[1] * ap[0];
-  if (c > 0) v = v - lo[0] * ap[-1];
-  if (c < mx - 1) v = v - lo[2] * ap[1];
+  cplx<double> v = t[(i + 1) * mx + c] - lower(i + 1, c, 1) * ap[0];
+  if (c > 0) v = v - lower(i + 1, c, 0) * ap[-1];
+  if (c < mx - 1) v = v - lower(i + 1, c, 2) * ap[1];
   t[(i + 1) * mx + c] = v;
 }
 
 // t_{i-1} -= U_{i-1} b_i (bottom) for unknown c, U_{i-1} read as L_i^T.
-__device__ __forceinline__ void tw_couple_up(int mx, const cplx<double>* lc, int i, int c, cplx<double>* t,
+template <typename Lower>
+__device__ __forceinline__ void tw_couple_up(int mx, Lower lower, int i, int c, cplx<double>* t,
                                              const cplx<double>* a) {
-  const cplx<double>* lo = lc + 3 * (i * mx + c);
   const cplx<double>* bp = a + i * mx + c;
-  cplx<double> v = t[(i - 1) * mx + c] - lo[1] * bp[0];
-  if (c > 0) v = v - lo[-3 + 2] * bp[-1];
-  if (c < mx - 1) v = v - lo[3 + 0] * bp[1];
+  cplx<double> v = t[(i - 1) * mx + c] - lower(i, c, 1) * bp[0];
+  if (c > 0) v = v - lower(i, c - 1, 2) * bp[-1];
+  if (c < mx - 1) v = v - lower(i, c + 1, 0) * bp[1];
   t[(i - 1) * mx + c] = v;
 }
 
 // t_p -= L_p a_{p-1} + U_p b_{p+1} for unknown c.
-__device__ __forceinline__ void tw_couple_middle(int mx, int my, int p, const cplx<double>* lc, int c,
-                                                 cplx<double>* t, const cplx<double>* a) {
-  if (p > 0) tw_couple_down(mx, lc, p - 1, c, t, a);
-  if (p < my - 1) tw_couple_up(mx, lc, p + 1, c, t, a);
+template <typename Lower>
+__device__ __forceinline__ void tw_couple_middle(int mx, int my, int p, Lower lower, int c, cplx<double>* t,
+                                                 const cplx<double>* a) {
+  if (p > 0) tw_couple_down(mx, lower, p - 1, c, t, a);
+  if (p < my - 1) tw_couple_up(mx, lower, p + 1, c, t, a);
 }
 
 // Factor blocks of Depth consecutive steps are loaded together into registers (clamped
 // indices, straight-line code) before those steps run.  Lane l of row group r of a half
 // owns columns l + q L, q < Q (mx <= L Q, rows Half / L >= mx).
-template <int L, int Q, int Depth, int Half>
-__device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<double>* __restrict__ F,
-                                                   const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
+template <int L, int Q, int Depth, int Half, typename Lower>
+__device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<double>* __restrict__ F, Lower lower,
+                                                   cplx<double>* t, cplx<double>* a) {
   const int mm = mx * mx, p = twist_row(my), nf = my - 1 - p, nsteps = 2 * nf + 1;
   const int h = threadIdx.x / Half, ht = threadIdx.x % Half;
   const int r = ht / L, l = ht % L;
@@ -314,14 +183,14 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
         lds_barrier();
         if (ht < mx) {
           if (h == 0) {
-            if (s + 1 < p) tw_couple_down(mx, lc, s, ht, t, a);
+            if (s + 1 < p) tw_couple_down(mx, lower, s, ht, t, a);
           } else {
-            if (i - 1 > p) tw_couple_up(mx, lc, i, ht, t, a);
+            if (i - 1 > p) tw_couple_up(mx, lower, i, ht, t, a);
           }
         }
         lds_barrier();
       } else if (s == nf) {
-        if (h == 0 && ht < mx) tw_couple_middle(mx, my, p, lc, ht, t, a);
+        if (h == 0 && ht < mx) tw_couple_middle(mx, my, p, lower, ht, t, a);
         lds_barrier();
         cplx<double> acc = czero<double>();
         if (h == 0) {
@@ -356,9 +225,9 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
 
 // Same steps for any mx <= kMaxMx: factor entries read as they are used, shuffle
 // reductions over groups of L = coarse_group_lanes<Half>(mx) lanes.
-template <int Half>
-__device__ __forceinline__ void twisted_solve_plain(int mx, int my, const cplx<double>* __restrict__ F,
-                                                    const cplx<double>* lc, cplx<double>* t, cplx<double>* a) {
+template <int Half, typename Lower>
+__device__ __forceinline__ void twisted_solve_plain(int mx, int my, const cplx<double>* __restrict__ F, Lower lower,
+                                                    cplx<double>* t, cplx<double>* a) {
   const int mm = mx * mx, p = twist_row(my), nf = my - 1 - p, nsteps = 2 * nf + 1;
   const int L = coarse_group_lanes<Half>(mx);
   const int h = threadIdx.x / Half, ht = threadIdx.x % Half;
@@ -386,14 +255,14 @@ __device__ __forceinline__ void twisted_solve_plain(int mx, int my, const cplx<d
       lds_barrier();
       if (ht < mx) {
         if (h == 0) {
-          if (s + 1 < p) tw_couple_down(mx, lc, s, ht, t, a);
+          if (s + 1 < p) tw_couple_down(mx, lower, s, ht, t, a);
         } else {
-          if (i - 1 > p) tw_couple_up(mx, lc, i, ht, t, a);
+          if (i - 1 > p) tw_couple_up(mx, lower, i, ht, t, a);
         }
       }
       lds_barrier();
     } else if (s == nf) {
-      if (h == 0 && ht < mx) tw_couple_middle(mx, my, p, lc, ht, t, a);
+      if (h == 0 && ht < mx) tw_couple_middle(mx, my, p, lower, ht, t, a);
       lds_barrier();
       const cplx<double> acc = product(tw_M(my), t + p * mx);
       if (h == 0 && active && l == 0) a[p * mx + r] = acc;
@@ -474,11 +343,12 @@ __device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double
   }
   // the two halves run the two sweeps: 512 threads give 8 lanes per block row (mx <= 32)
   // and a ring of 8 steps, 256 threads 4 lanes and a ring of 4 (register budget)
+  auto lower = [lc, mx = d.mx](int i, int c, int e) { return lc[3 * (i * mx + c) + e]; };
   if (d.mx <= 32) {
-    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 8, NT / 2>(d.mx, d.my, F, lc, t, a);
-    else detail::twisted_solve_ring<4, 8, 4, NT / 2>(d.mx, d.my, F, lc, t, a);
+    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 8, NT / 2>(d.mx, d.my, F, lower, t, a);
+    else detail::twisted_solve_ring<4, 8, 4, NT / 2>(d.mx, d.my, F, lower, t, a);
   } else {
-    detail::twisted_solve_plain<NT / 2>(d.mx, d.my, F, lc, t, a);
+    detail::twisted_solve_plain<NT / 2>(d.mx, d.my, F, lower, t, a);
   }
 }
 

@@ -4,11 +4,13 @@
 // With the tile's nodes ordered x fastest, the local P1 matrix B_j is block tridiagonal
 // in the rows of the tile: diagonal blocks couple a row to itself (W, C, E), the lower
 // block a row to the row below (S and SW for the SW->NE cell diagonal), the upper block
-// to the row above (N, NE).  The same block LU as the coarse deflation matrices
-// (coarse.hpp: inverted Schur blocks G_i, H_i = G_i U_i) is built at set-up, once per
-// subdomain, and every solve is 2 ny - 1 dense nx x nx products.  One workgroup per
-// (subdomain, right-hand side): gather R_j r, forward and backward block sweeps with the
-// lower couplings taken from the stencil's row classes, scatter of the owned nodes.
+// to the row above (N, NE).  B_j is complex symmetric, and the same twisted block
+// factorisation as the coarse deflation matrices (coarse.hpp: elimination from both ends
+// towards the middle row, upper couplings read as the transposed lower ones) is built at
+// set-up, once per subdomain; every solve is ny sequential dense nx x nx products, the
+// two sweeps side by side.  One workgroup per (subdomain, right-hand side): gather R_j r,
+// the block sweeps with the lower couplings taken from the stencil's row classes, scatter
+// of the owned nodes.
 #include "coarse.hpp"
 #include "kernels.hpp"
 #include "stencil.hpp"
@@ -79,11 +81,10 @@ __global__ void __launch_bounds__(NT) direct_solve_kernel(DirectArgs a) {
     return tab[cls * kStencilPts + (e == 0 ? kSW : kS)];
   };
   const cplx<double>* __restrict__ F = a.ffac + a.foff[sub];
-  const int L = coarse_group_lanes<NT>(nx);
-  const int Q = (nx + L - 1) / L;
-  if (L == 16 && Q <= 2) detail::block_solve_ring<16, 2, kCoarseBatch>(nx, ny, F, lower, t, x);
-  else if (L == 8 && Q <= 8) detail::block_solve_ring<8, 8, 2>(nx, ny, F, lower, t, x);
-  else detail::block_solve_plain<NT>(nx, ny, F, lower, t, x);
+  // the two halves of the workgroup run the two sweeps of the twisted factorisation
+  if (nx <= 32) detail::twisted_solve_ring<8, 4, 8, NT / 2>(nx, ny, F, lower, t, x);
+  else if (nx <= 64) detail::twisted_solve_ring<4, 16, 2, NT / 2>(nx, ny, F, lower, t, x);
+  else detail::twisted_solve_plain<NT / 2>(nx, ny, F, lower, t, x);
   for (int n = tid; n < nj; n += NT) {
     if (a.U) a.U[(long long)rhs * a.nfine + d.off + n] = x[n];
     if (zout) {

@@ -8,10 +8,8 @@ namespace ddh {
 // ---- set-up -----------------------------------------------------------------
 hipError_t launch_assemble_coarse(const SubDesc* subs, int nsub, Consts cs, int local_bc, cplx<double>* Ec,
                                   hipStream_t st);
-hipError_t launch_factor_coarse(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
-                                double* pivmin, hipStream_t st);
-// Twisted block factorisation of E (linear deflation); the one-ended block LU
-// (launch_factor_coarse) serves the exact local solves.
+// Twisted block factorisation of E (linear deflation) or, through per-subdomain views, of
+// the local matrices of the exact solves.
 hipError_t launch_factor_coarse_twisted(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
                                         double* pivmin, hipStream_t st);
 hipError_t launch_factor_coarse_paired(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
@@ -147,7 +145,7 @@ struct DirectArgs {
   const int* order;              // launch order (size nsub * nrhs) or null
   Consts cs;
   int local_bc;
-  const cplx<double>* ffac;      // block-LU factors of the local matrices
+  const cplx<double>* ffac;      // twisted block factors of the local matrices
   const long long* foff;         // [nsub] factor offsets (complex<double> elements)
   const cplx<double>* r;         // global right-hand sides, or null: use F
   cplx<double>* z;               // global output (owned nodes), or null

@@ -102,56 +102,6 @@ __device__ double gauss_jordan_inverse(cplx<double>* A, int n, int* perm, cplx<d
   return minpiv;
 }
 
-__global__ void __launch_bounds__(kBlock) factor_coarse_kernel(const SubDesc* __restrict__ subs,
-                                                                const cplx<double>* __restrict__ Ec,
-                                                                cplx<double>* __restrict__ fac,
-                                                                double* __restrict__ pivmin) {
-  const SubDesc d = subs[blockIdx.x];
-  __shared__ int perm[kMaxMx];
-  __shared__ cplx<double> colp[kMaxMx];
-  __shared__ double pivabs;
-  const int mx = d.mx, my = d.my, mm = mx * mx, tid = threadIdx.x;
-  const cplx<double>* ec = Ec + d.coff * 9;
-  cplx<double>* F = fac + d.goff;
-  double minp = 1e300;
-  for (int i = 0; i < my; ++i) {
-    cplx<double>* G = F + (size_t)i * mm;
-    const cplx<double>* Hprev = F + (size_t)(my + i - 1) * mm;
-    // S_i = D_i - L_i H_{i-1}
-    for (int e = tid; e < mm; e += blockDim.x) {
-      const int r = e / mx, c = e - r * mx;
-      const cplx<double>* row = ec + (size_t)(i * mx + r) * 9;
-      cplx<double> s = (c - r >= -1 && c - r <= 1) ? row[3 + (c - r) + 1] : czero<double>();
-      if (i > 0) {
-        for (int dr = -1; dr <= 1; ++dr) {
-          const int rr = r + dr;
-          if (rr >= 0 && rr < mx) s = s - row[dr + 1] * Hprev[rr * mx + c];
-        }
-      }
-      G[r * mx + c] = s;
-    }
-    __syncthreads();
-    minp = fmin(minp, gauss_jordan_inverse(G, mx, perm, colp, &pivabs));
-    if (i < my - 1) {
-      // H_i = G_i U_i, U_i(cc, c) = coupling of row-i node cc to row-(i+1) node c
-      cplx<double>* H = F + (size_t)(my + i) * mm;
-      for (int e = tid; e < mm; e += blockDim.x) {
-        const int r = e / mx, c = e - r * mx;
-        cplx<double> s = czero<double>();
-        for (int dc = -1; dc <= 1; ++dc) {
-          const int cc = c + dc;
-          if (cc < 0 || cc >= mx) continue;
-          const cplx<double> u = ec[(size_t)(i * mx + cc) * 9 + 6 + (c - cc) + 1];
-          s = s + G[r * mx + cc] * u;
-        }
-        H[r * mx + c] = s;
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) pivmin[blockIdx.x] = minp;
-}
-
 // Twisted block factorisation of E (linear deflation; layout and relations in
 // coarse.hpp).  D_i from the stored own-row couplings, L_i from the stored lower
 // couplings, U_i = L_{i+1}^T.
@@ -313,10 +263,5 @@ hipError_t launch_assemble_coarse(const SubDesc* subs, int nsub, Consts cs, int 
   return hipGetLastError();
 }
 
-hipError_t launch_factor_coarse(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
-                                double* pivmin, hipStream_t st) {
-  hipLaunchKernelGGL(factor_coarse_kernel, dim3(nsub), dim3(kBlock), 0, st, subs, Ec, fac, pivmin);
-  return hipGetLastError();
-}
 
 }  // namespace ddh
