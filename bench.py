@@ -21,7 +21,7 @@ kernel, in one more solve of the same handle and inputs with the steps launched 
 by one right after the timed solves (HIP cannot time events inside graph replays);
 `roofline` is the one with the largest total time.  The CPU baseline is the oracle timed on a
 bounded sample of the same workload (its first outer iterations).  `direct_local_solves`
-times the same solve with exact subdomain solves (FP64 block LU of every local matrix, the
+times the same solve with exact subdomain solves (FP64 block factorisation of every local matrix, the
 direct-solve baseline of the paper's experiments) for comparison; `two_level` times the
 two-level method (a global coarse space added to the chosen form, the extension the
 paper proposes in its conclusions).
@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
     ap.add_argument("--no-plain", action="store_true", help="skip the all-FP64 comparison solve")
     ap.add_argument("--no-direct", action="store_true",
-                    help="skip the comparison with exact (FP64 block-LU) subdomain solves")
+                    help="skip the comparison with exact (FP64 block-factorised) subdomain solves")
     ap.add_argument("--no-two-level", action="store_true",
                     help="skip the two-level solve (global coarse space of --coarse-intervals per edge)")
     ap.add_argument("--coarse-intervals", type=int, default=0,
@@ -289,7 +289,7 @@ def main():
                              "form": "complex128 inner in the fused batched kernel, steps launched one by one"}
         fused.close()
     if not args.no_direct:
-        # the paper's direct-solve baseline: exact FP64 subdomain solves (block LU of each B_j)
+        # the paper's direct-solve baseline: exact FP64 subdomain solves (block factorisation of each B_j)
         direct = make_solver(w, 64, "direct")
         td, ud, sd = timed_solves(torch, direct, f, 1, 1)
         direct.set_graph(False)

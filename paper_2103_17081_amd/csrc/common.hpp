@@ -82,7 +82,7 @@ struct SubDesc {
   int mx, my;        // coarse grid mx * my (coarse node c on fine node 2c + 1 per direction)
   int robin;
   int defl;          // deflation vectors: 0 linear interpolation, 1 quadratic Bezier
-  int bmx, bmy;      // block LU of E: bmy block rows of bmx unknowns (linear: mx, my;
+  int bmx, bmy;      // block factorisation of E: bmy block rows of bmx unknowns (linear: mx, my;
                      // Bezier: pairs of coarse rows, 2 mx and ceil(my / 2))
   int ncp;           // coarse vector length of the solve, bmx * bmy (>= mx * my)
   int pad;

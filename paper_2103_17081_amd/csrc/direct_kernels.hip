@@ -1,4 +1,4 @@
-// Exact subdomain solves with an FP64 block LU of each local matrix: the direct-solve
+// Exact subdomain solves with an FP64 block factorisation of each local matrix: the direct-solve
 // baseline against which the paper measures its inexact solves (Sec. 3, Table 1).
 //
 // With the tile's nodes ordered x fastest, the local P1 matrix B_j is block tridiagonal

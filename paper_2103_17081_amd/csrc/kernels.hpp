@@ -25,7 +25,7 @@ struct InnerArgs {
   const int* order;              // launch order of the solves (size nsub * nrhs), or null
   Consts cs;
   int local_bc;                  // 0 impedance, 1 Dirichlet
-  const cplx<double>* fac;       // coarse block-LU factors
+  const cplx<double>* fac;       // coarse block factors (twisted; paired rows for Bezier)
   const cplx<double>* Ec;        // coarse 9-point coefficients
   const cplx<double>* r;         // global right-hand sides [nrhs][ndof], or null: use F
   cplx<double>* z;               // global output [nrhs][ndof] (owned nodes), or null
@@ -96,7 +96,7 @@ struct MultiArgs {
   const SubDesc* subs;
   Consts cs;
   int local_bc;
-  const cplx<double>* fac;       // coarse block-LU factors
+  const cplx<double>* fac;       // coarse block factors (twisted; paired rows for Bezier)
   const cplx<double>* Ec;        // coarse 9-point coefficients
   const cplx<double>* r;         // global right-hand side [ndof], or null: use F (unscaled, scaled in place)
   cplx<double>* z;               // global output (owned nodes), or null
@@ -139,7 +139,7 @@ struct MultiArgs {
 // active_host: pinned host int the loop reads the active count into.
 hipError_t run_multi_inner(const MultiArgs& a, int* active_host, hipStream_t st);
 
-// ---- exact subdomain solves (FP64 block LU of the local matrices) ---------------------
+// ---- exact subdomain solves (FP64 twisted block factorisation of the local matrices) ---
 struct DirectArgs {
   const SubDesc* subs;
   const int* order;              // launch order (size nsub * nrhs) or null

@@ -63,7 +63,6 @@ hipError_t launch_update(const cplx<double>* basis, long long bstride, cplx<doub
 hipError_t launch_scale(const cplx<double>* w, long long wstride, cplx<double>* out, long long ostride,
                         long long ndof, const double* scale, int nblk, int nrhs, const int* done,
                         hipStream_t st);
-hipError_t launch_givens(const OuterState& s, int j, int nrhs, hipStream_t st);
 hipError_t launch_dots2(const cplx<double>* basis, long long bstride, const cplx<double>* x1, long long x1stride,
                         const cplx<double>* x2, long long x2stride, long long ndof, StepRef sr, int two, int jmax,
                         cplx<double>* part, int pstride, int nrhs, const int* done, hipStream_t st,

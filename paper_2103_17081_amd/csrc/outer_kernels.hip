@@ -617,68 +617,7 @@ __global__ void __launch_bounds__(256) scale_kernel(const cplx<double>* w, long 
     out[rhs * ostride + n] = inv * w[rhs * wstride + n];
 }
 
-// Givens step j of every active right-hand side (one workgroup each).
-// H column j (j+1 entries) is in st.H; the norm^2 of the orthogonalised w in
-// nrm2[rhs].  Applies the stored rotations, forms rotation j, updates g, stores the
-// rotated column into R (column j), sets res[rhs] = |g_{j+1}| and done[rhs] when
-// res <= atol[rhs], and hnext[rhs] = ||w||.  The column and the rotations are staged
-// through LDS so the sequential sweep runs at LDS latency.
-constexpr int kGivensMax = 4000;
-__global__ void __launch_bounds__(256) givens_kernel(OuterState st, int j) {
-  const int rhs = blockIdx.x;
-  if (st.done[rhs]) return;
-  extern __shared__ __align__(16) unsigned char gsm[];
-  const int m = st.restart;
-  cplx<double>* lcol = (cplx<double>*)gsm;
-  cplx<double>* lsn = lcol + (j + 2);
-  double* lcs = (double*)(lsn + (j + 1));
-  cplx<double>* col = st.H + (long long)rhs * (m + 1);
-  double* cs = st.cs + (long long)rhs * m;
-  cplx<double>* sn = st.sn + (long long)rhs * m;
-  cplx<double>* g = st.g + (long long)rhs * (m + 1);
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-    lcol[i] = col[i];
-    if (i < j) { lsn[i] = sn[i]; lcs[i] = cs[i]; }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double hnext = sqrt(st.nrm2[rhs * st.nrm_stride].re);
-    for (int i = 0; i < j; ++i) {
-      const cplx<double> x0 = lcol[i], x1 = lcol[i + 1];
-      lcol[i] = lcs[i] * x0 + lsn[i] * x1;
-      lcol[i + 1] = lcs[i] * x1 - cplx<double>{lsn[i].re, -lsn[i].im} * x0;
-    }
-    const cplx<double> av = lcol[j];
-    const double aa = sqrt(cabs2(av));
-    double c;
-    cplx<double> s, r;
-    if (hnext == 0.0) {
-      c = 1.0; s = czero<double>(); r = av;
-    } else if (aa == 0.0) {
-      c = 0.0; s = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
-    } else {
-      const double t = hypot(aa, hnext);
-      const cplx<double> ph{av.re / aa, av.im / aa};
-      c = aa / t;
-      s = (hnext / t) * ph;
-      r = t * ph;
-    }
-    cs[j] = c;
-    sn[j] = s;
-    lcol[j] = r;
-    const cplx<double> gj = g[j];
-    g[j + 1] = czero<double>() - cplx<double>{s.re, -s.im} * gj;
-    g[j] = c * gj;
-    const double res = sqrt(cabs2(g[j + 1]));
-    st.res[rhs] = res;
-    st.hnext[rhs] = hnext;
-    st.steps[rhs] = j + 1;
-    if (res <= st.atol[rhs] || hnext == 0.0) st.done[rhs] = 1;
-  }
-  __syncthreads();
-  cplx<double>* R = st.R + (long long)rhs * m * m + (long long)j * m;
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) R[i] = lcol[i];
-}
+constexpr int kGivensMax = 4000;   // longest outer cycle the bookkeeping stages in LDS
 
 // y = R^{-1} g over the first steps[rhs] columns (one workgroup per right-hand side,
 // column-oriented back substitution: after y_i is known every thread updates its rows).
@@ -740,10 +679,7 @@ hipError_t launch_fill_hash(cplx<double>* x, long long n, unsigned long long see
 
 hipError_t configure_outer() {
   const int lds = (int)((size_t)(kGivensMax + 2) * 40);
-  hipError_t e = hipFuncSetAttribute((const void*)dcgs2_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)givens_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  return e;
+  return hipFuncSetAttribute((const void*)dcgs2_step_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 
@@ -815,12 +751,6 @@ hipError_t launch_dcgs2_update(cplx<double>* basis, long long bstride, long long
   return hipGetLastError();
 }
 
-hipError_t launch_givens(const OuterState& s, int j, int nrhs, hipStream_t st) {
-  if (j + 1 > kGivensMax) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(j + 2) * sizeof(cplx<double>) + (size_t)(j + 1) * (sizeof(cplx<double>) + sizeof(double));
-  hipLaunchKernelGGL(givens_kernel, dim3(nrhs), dim3(256), lds, st, s, j);
-  return hipGetLastError();
-}
 
 hipError_t launch_backsolve(const OuterState& s, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(backsolve_kernel, dim3(nrhs), dim3(256), 0, st, s);

@@ -1,5 +1,5 @@
 // Set-up kernels: Galerkin coarse matrices E_j = Z_j^T B_j Z_j and their FP64
-// block LU (see coarse.hpp).  One workgroup per subdomain.
+// block factorisations (see coarse.hpp).  One workgroup per subdomain.
 #include "coarse.hpp"
 #include "kernels.hpp"
 #include "stencil.hpp"
