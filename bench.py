@@ -22,7 +22,9 @@ by one right after the timed solves (HIP cannot time events inside graph replays
 `roofline` is the one with the largest total time.  The CPU baseline is the oracle timed on a
 bounded sample of the same workload (its first outer iterations).  `direct_local_solves`
 times the same solve with exact subdomain solves (FP64 block factorisation of every local matrix, the
-direct-solve baseline of the paper's experiments) for comparison; `two_level` times the
+direct-solve baseline of the paper's experiments) for comparison; `learned_guess` times the
+chosen form with the trained BF16 guess network attached (its output offered to every
+subdomain GMRES, kept only when it lowers the deflated residual); `two_level` times the
 two-level method (a global coarse space added to the chosen form, the extension the
 paper proposes in its conclusions).
 """
@@ -78,6 +80,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
     ap.add_argument("--no-plain", action="store_true", help="skip the all-FP64 comparison solve")
+    ap.add_argument("--no-guess", action="store_true", help="skip the solve with the learned initial guess")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the comparison with exact (FP64 block-factorised) subdomain solves")
     ap.add_argument("--no-two-level", action="store_true",
@@ -140,6 +143,37 @@ def cpu_baseline(w, outer: int):
             "sample": f"first {st.outer_iters} outer FGMRES iterations of workload '{w.name}' "
                       f"({st.subdomain_solves} subdomain solves, avg {st.avg_inner:.1f} inner its) "
                       f"in {dt:.1f} s; setup excluded; BLAS threads {threads or 'default'}"}
+
+
+GUESS_WEIGHTS = os.path.join(ROOT, "paper_2103_17081_amd", "weights", "guess_t64.ddnet")
+
+
+def guess_leg(torch, w, f, t_zero: float):
+    """The chosen form with the learned initial guess attached (the trained BF16 network's
+    output offered to every subdomain GMRES, kept only when it lowers the deflated
+    residual); t_zero (s) is the zero-guess chosen form's time to solution."""
+    from paper_2103_17081_amd.guess import load_net
+    s = make_solver(w, 32)
+    s.autotune(None)
+    net = load_net(GUESS_WEIGHTS, max_batch=s.nsub * s.nrhs)
+    s.set_guess(net)
+    tg, ug, sg = timed_solves(torch, s, f, 1, 1)
+    s.set_graph(False)
+    _, gi = s.solve(f)
+    torch.cuda.synchronize()
+    last = sg[-1]
+    out = {"weights": os.path.relpath(GUESS_WEIGHTS, ROOT), "time_to_solution_s": tg,
+           "outer_iters": last["outer_iters"],
+           "avg_inner_iters": last["inner_iters_total"] / max(last["subdomain_solves"], 1),
+           "guesses_accepted_frac": last["guesses_accepted"] / max(last["subdomain_solves"], 1),
+           "true_relres": true_relres(torch, s, f, ug), "status": last["status"],
+           "ms_per_step_guess": gi["ms_guess"] / max(gi["timed_steps"], 1),
+           "ms_per_step_inner": gi["ms_inner"] / max(gi["timed_steps"], 1),
+           "speedup_vs_zero_guess": t_zero / tg}
+    s.set_guess(None)
+    s.close()
+    net.close()
+    return out
 
 
 def two_level_leg(torch, w, f, M: int, t_one_level=None, direct: bool = True):
@@ -302,6 +336,8 @@ def main():
             "ms_per_precond_apply": di["ms_inner"] / max(di["precond_applies"], 1),
             "algorithmic_GB_per_apply": di["inner_bytes"] / max(di["precond_applies"], 1) / 1e9}
         direct.close()
+    if not args.no_guess:
+        out["learned_guess"] = guess_leg(torch, w, f, t / args.steps)
     if not args.no_two_level:
         out["two_level"] = two_level_leg(torch, w, f, args.coarse_intervals or default_coarse_intervals(w),
                                          t / args.steps)
