@@ -218,8 +218,9 @@ __global__ void __launch_bounds__(kInvThreads) gc_inverse_kernel(const InvTask* 
 // with the matrices stored transposed, so lane r of each of the 256 / RPB column slices
 // reads entries (k, row0 + r) of consecutive rows: coalesced, one output row per lane,
 // the slices summed through LDS at the end.  Every matrix entry is read once for all
-// right-hand sides of a group of kBcrRhsGroup.
-template <int RPB, int NT>
+// right-hand sides of a group of kBcrRhsGroup.  Each lane keeps CH columns of every
+// term in flight per pass (chosen per launch shape by timing whole two-level solves).
+template <int RPB, int NT, int CH>
 __global__ void __launch_bounds__(NT) gc_bcr_kernel(const BcrTask* __restrict__ tasks, int first,
                                                     const double* __restrict__ fac, cplx<double>* cv,
                                                     long long cvstride, int n, int nrhs) {
@@ -240,7 +241,6 @@ __global__ void __launch_bounds__(NT) gc_bcr_kernel(const BcrTask* __restrict__ 
       // chunks of CH columns per lane for all terms at once, every load in flight
       // together (indices past the end are clamped and their entries zeroed, so every
       // load stays in bounds)
-      constexpr int CH = 8;
       for (int k0 = sl; k0 < n; k0 += CH * S) {
         double mk[3][CH];
 #pragma unroll
@@ -741,18 +741,21 @@ hipError_t GlobalCoarse::solve(int nr, hipStream_t st) {
       GC_TRY(hipGetLastError());
       continue;
     }
-    // Rows per workgroup (measured on the k = 200, N = 637, M = 318 solve): 64 (4 column
-    // slices) when the level has many tasks, 16 (16 slices) down to 8 tasks, 4 (64
-    // slices) on the last levels, where the launch is bound by load latency.
+    // Rows per workgroup and columns in flight per lane (measured on the k = 200, N = 637,
+    // M = 318 solve): 64 rows (4 column slices, 16 columns each) when the level has many
+    // tasks, 16 (16 slices, 5 columns) down to 8 tasks, 4 (64 slices, 5 columns) on the last
+    // levels, where the launch is bound by load latency.  A pass then covers 64, 80 and 320
+    // columns: whole passes over the 317 columns of that solve, and 2.6x the loads in flight
+    // of 8 columns per lane at the widest shape (coarse solve 0.49 -> 0.34 ms).
     const long long c = ph.count;
     if (c * ((nc + 63) / 64) >= 384) {
-      hipLaunchKernelGGL((gc_bcr_kernel<64, 256>), dim3((unsigned)((nc + 63) / 64), (unsigned)c), dim3(256), 0, st,
+      hipLaunchKernelGGL((gc_bcr_kernel<64, 256, 16>), dim3((unsigned)((nc + 63) / 64), (unsigned)c), dim3(256), 0, st,
                          (const BcrTask*)tasks, ph.first, (const double*)fac, cv, 2 * ncoarse, nc, nr);
     } else if (c >= 8) {
-      hipLaunchKernelGGL((gc_bcr_kernel<16, 256>), dim3((unsigned)((nc + 15) / 16), (unsigned)c), dim3(256), 0, st,
+      hipLaunchKernelGGL((gc_bcr_kernel<16, 256, 5>), dim3((unsigned)((nc + 15) / 16), (unsigned)c), dim3(256), 0, st,
                          (const BcrTask*)tasks, ph.first, (const double*)fac, cv, 2 * ncoarse, nc, nr);
     } else {
-      hipLaunchKernelGGL((gc_bcr_kernel<4, 256>), dim3((unsigned)((nc + 3) / 4), (unsigned)c), dim3(256), 0, st,
+      hipLaunchKernelGGL((gc_bcr_kernel<4, 256, 5>), dim3((unsigned)((nc + 3) / 4), (unsigned)c), dim3(256), 0, st,
                          (const BcrTask*)tasks, ph.first, (const double*)fac, cv, 2 * ncoarse, nc, nr);
     }
     GC_TRY(hipGetLastError());
