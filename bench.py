@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
     ap.add_argument("--no-plain", action="store_true", help="skip the all-FP64 comparison solve")
     ap.add_argument("--no-guess", action="store_true", help="skip the solve with the learned initial guess")
+    ap.add_argument("--xlarge-batches", action="store_true",
+                    help="only: the k = 400 grid's eight right-hand sides with the two-level method (M = N/2), "
+                         "as two unrestarted batches of four, chosen form and exact local solves")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the comparison with exact (FP64 block-factorised) subdomain solves")
     ap.add_argument("--no-two-level", action="store_true",
@@ -176,6 +179,42 @@ def guess_leg(torch, w, f, t_zero: float):
     return out
 
 
+def xlarge_batches(torch, batch: int = 4, maxit: int = 1000):
+    """The largest one-GPU configuration (k = 400, N = 1274, 32 x 32 blocks, eight right-hand
+    sides) with the two-level method, M = N/2.  Unrestarted FGMRES keeps 2 x 26 MB of FP64
+    bases per right-hand side and column, so the eight are solved as batches of `batch`."""
+    import numpy as np
+    from paper_2103_17081_amd import inputs
+    from paper_2103_17081_amd.binding import Solver
+    w = inputs.workload("xlarge", 8)
+    F_all = torch.from_numpy(np.stack(w.rhs)).to("cuda")
+    out = {"workload": f"xlarge: k={w.k:g}, N={w.n} ({w.ndof} dofs), {w.nsub} subdomains, 8 right-hand sides",
+           "coarse_intervals": default_coarse_intervals(w), "batch": batch, "outer_maxit": maxit}
+    for form, prec, local in (("chosen", 32, "deflated"), ("exact_local_solves", 64, "direct")):
+        tot, runs = 0.0, []
+        for b0 in range(0, len(w.rhs), batch):
+            F = F_all[b0:b0 + batch].contiguous()
+            s = Solver(w.k, n_intervals=w.n, cuts_x=w.cuts_x, cuts_y=w.cuts_y, overlap=w.overlap,
+                       inner_precision=prec, inner_tol=w.inner_tol, outer_tol=w.outer_tol, outer_maxit=maxit,
+                       nrhs=batch, coarse_intervals=default_coarse_intervals(w), local_solver=local)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U, st = s.solve(F)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            R = F - torch.stack([s.op_global_apply(U[q].contiguous()) for q in range(batch)])
+            rel = (torch.linalg.vector_norm(R, dim=1) / torch.linalg.vector_norm(F, dim=1)).max().item()
+            s.close()
+            del U, R
+            torch.cuda.empty_cache()
+            tot += dt
+            runs.append({"rhs": [b0, b0 + batch], "time_to_solution_s": dt, "outer_iters": st["outer_iters"],
+                         "true_relres_max": rel, "status": st["status"]})
+            print(json.dumps({form: runs[-1]}), flush=True)
+        out[form] = {"time_to_solution_s": tot, "batches": runs}
+    return out
+
+
 def two_level_leg(torch, w, f, M: int, t_one_level=None, direct: bool = True):
     """The two-level method (global coarse space of M intervals per edge) in the chosen
     form, and with exact subdomain solves; t_one_level (s) gives the speedups."""
@@ -234,6 +273,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.xlarge_batches:
+        print(json.dumps({"xlarge_batches": xlarge_batches(torch)}), flush=True)
+        return 0
     if args.two_level_only:
         M = args.coarse_intervals or default_coarse_intervals(w)
         print(json.dumps({"two_level": two_level_leg(torch, w, f, M, direct=not args.no_direct)}), flush=True)
