@@ -26,7 +26,9 @@ direct-solve baseline of the paper's experiments) for comparison; `learned_guess
 chosen form with the trained BF16 guess network attached (its output offered to every
 subdomain GMRES, kept only when it lowers the deflated residual); `two_level` times the
 two-level method (a global coarse space added to the chosen form, the extension the
-paper proposes in its conclusions).
+paper proposes in its conclusions).  `--xlarge-batches` runs only the largest one-GPU
+configuration (k = 400, eight right-hand sides) with the two-level method, as two
+unrestarted batches of four.
 """
 
 from __future__ import annotations
