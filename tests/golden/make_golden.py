@@ -1,6 +1,7 @@
 """Write tests/golden/oracle_counts.json from the oracle alone.
 
 Usage: python tests/golden/make_golden.py small [medium] [large]
+       python tests/golden/make_golden.py --tol-sweep medium 0.1 0.0001
        python tests/golden/make_golden.py --spread small [medium]
        python tests/golden/make_golden.py --direct small [medium] [large]
        python tests/golden/make_golden.py --two-level small:16 [medium:80]
@@ -37,7 +38,21 @@ OUT = os.path.join(HERE, "oracle_counts.json")
 EPS32 = 2.0 ** -24   # complex64 unit roundoff
 
 
-def spread(name, seeds=8):
+def store(path, update):
+    """Apply update(data) to the JSON file at path, re-read under an exclusive lock just
+    before writing, so that oracle runs started side by side keep each other's entries."""
+    import fcntl
+    with open(path + ".lock", "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        data = json.load(open(path)) if os.path.exists(path) else {}
+        update(data)
+        with open(path + ".tmp", "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+        os.replace(path + ".tmp", path)
+    return data
+
+
+def spread(name, seeds=8, tol=None):
     """Outer counts of the oracle when its subdomain solves are perturbed at FP32 level.
 
     Mode "round": local right-hand sides and local solutions rounded to complex64.
@@ -47,6 +62,7 @@ def spread(name, seeds=8):
     import numpy as np
     from oracle import krylov
     w = inputs.workload(name)
+    tol = w.inner_tol if tol is None else tol
     S = schwarz.Schwarz(schwarz.problem_from_workload(w))
     r32 = lambda x: x.astype(np.complex64).astype(np.complex128)
 
@@ -54,7 +70,7 @@ def spread(name, seeds=8):
         def apply(r):
             us = []
             for s, f in zip(S.subs, S.local_rhs(r)):
-                u, _, _ = s.deflated_gmres(pre(f), w.inner_tol, 100)
+                u, _, _ = s.deflated_gmres(pre(f), tol, 100)
                 us.append(post(u))
             return S.scatter(us)
         return krylov.fgmres(lambda v: S.A @ v, apply, w.rhs[0], rtol=w.outer_tol, maxit=5000).iters
@@ -70,17 +86,37 @@ def spread(name, seeds=8):
     return counts
 
 
+def solve_with_progress(S, w, inner_tol, label, every=50):
+    """The oracle's outer FGMRES (as Schwarz.solve runs it) with a progress line every
+    `every` preconditioner applications, for runs that take hours."""
+    import numpy as np
+    from oracle import krylov
+    st = schwarz.SolveStats()
+    count = [0]
+    t0 = time.time()
+
+    def precond(v):
+        count[0] += 1
+        if count[0] % every == 0:
+            print(f"{label}: {count[0]} applications, {time.time() - t0:.0f} s", flush=True)
+        return S.apply(v, "deflated", inner_tol, 200, st)
+
+    f = w.rhs[0]
+    res = krylov.fgmres(lambda v: S.A @ v, precond, f, rtol=w.outer_tol, maxit=5000)
+    st.outer_iters = res.iters
+    st.converged = res.converged
+    st.history = res.history
+    st.true_relres = float(np.linalg.norm(f - S.A @ res.x) / np.linalg.norm(f))
+    return st
+
+
 def main(names):
-    data = {}
-    if os.path.exists(OUT):
-        with open(OUT) as fh:
-            data = json.load(fh)
     for name in names:
         w = inputs.workload(name)
         S = schwarz.Schwarz(schwarz.problem_from_workload(w))
         t = time.time()
-        _, st = S.solve(w.rhs[0], mode="deflated", inner_tol=w.inner_tol, outer_maxit=5000)
-        data[name] = {
+        st = solve_with_progress(S, w, w.inner_tol, name)
+        entry = {
             "outer_iters": st.outer_iters,
             "inner_iters": st.inner_iters,
             "subdomain_solves": st.subdomain_solves,
@@ -89,23 +125,39 @@ def main(names):
             "outer_tol": w.outer_tol,
             "oracle_seconds": round(time.time() - t, 1),
         }
-        print(name, data[name], flush=True)
-        with open(OUT, "w") as fh:
-            json.dump(data, fh, indent=1, sort_keys=True)
+        # other keys of the entry (direct, two-level, spreads) are kept
+        store(OUT, lambda d: d.setdefault(name, {}).update(entry))
+        print(name, entry, flush=True)
+
+
+def tol_sweep(name, tols):
+    """The workload's one-level solve at other inner tolerances (the inner-tolerance study of
+    Sec. 3, Tables 2-4), with the spread of outer counts under FP32-level perturbations of
+    the subdomain solves at each tolerance; stored under entry["tol_sweep"][tol]."""
+    w = inputs.workload(name)
+    S = schwarz.Schwarz(schwarz.problem_from_workload(w))
+    for tol in tols:
+        t = time.time()
+        st = solve_with_progress(S, w, tol, f"{name} tol {tol:g}")
+        entry = {"outer_iters": st.outer_iters, "inner_iters": st.inner_iters,
+                 "subdomain_solves": st.subdomain_solves, "true_relres": st.true_relres,
+                 "inner_tol": tol, "outer_tol": w.outer_tol, "oracle_seconds": round(time.time() - t, 1)}
+        entry["fp32_perturbed_outer"] = spread(name, 2, tol)
+        key = f"{tol:g}"
+        store(OUT, lambda d: d.setdefault(name, {}).setdefault("tol_sweep", {}).update({key: entry}))
+        print(name, key, entry, flush=True)
 
 
 def direct(names):
-    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         w = inputs.workload(name)
         S = schwarz.Schwarz(schwarz.problem_from_workload(w))
         t = time.time()
         _, st = S.solve(w.rhs[0], mode="direct", outer_maxit=5000)
-        data.setdefault(name, {})["direct"] = {"outer_iters": st.outer_iters, "true_relres": st.true_relres,
-                                               "oracle_seconds": round(time.time() - t, 1)}
-        print(name, data[name]["direct"], flush=True)
-        with open(OUT, "w") as fh:
-            json.dump(data, fh, indent=1, sort_keys=True)
+        entry = {"outer_iters": st.outer_iters, "true_relres": st.true_relres,
+                 "oracle_seconds": round(time.time() - t, 1)}
+        store(OUT, lambda d: d.setdefault(name, {}).update({"direct": entry}))
+        print(name, entry, flush=True)
 
 
 def perturbed_two_level(T, w, seeds=4, eps=1e-12):
@@ -129,7 +181,6 @@ def perturbed_two_level(T, w, seeds=4, eps=1e-12):
 
 def two_level(specs):
     from oracle import coarse_space
-    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for spec in specs:
         name, m = spec.split(":")
         w = inputs.workload(name)
@@ -143,10 +194,8 @@ def two_level(specs):
             "oracle_seconds": round(time.time() - t, 1)}
         if name == "small":
             entry["coarse_perturbed_outer"] = perturbed_two_level(T, w)
-        data.setdefault(name, {}).setdefault("two_level", {})[m] = entry
-        print(name, m, data[name]["two_level"][m], flush=True)
-        with open(OUT, "w") as fh:
-            json.dump(data, fh, indent=1, sort_keys=True)
+        store(OUT, lambda d: d.setdefault(name, {}).setdefault("two_level", {}).update({m: entry}))
+        print(name, m, entry, flush=True)
 
 
 def paper_two_level():
@@ -187,11 +236,11 @@ if __name__ == "__main__":
     elif args and args[0] == "--direct":
         direct(args[1:] or ["small"])
     elif args and args[0] == "--spread":
-        data = json.load(open(OUT)) if os.path.exists(OUT) else {}
         for name in args[1:] or ["small"]:
-            data.setdefault(name, {})["fp32_perturbed_outer"] = spread(name, 8 if name == "small" else 2)
-            print(name, data[name]["fp32_perturbed_outer"], flush=True)
-            with open(OUT, "w") as fh:
-                json.dump(data, fh, indent=1, sort_keys=True)
+            sp = spread(name, 8 if name == "small" else 2)
+            store(OUT, lambda d: d.setdefault(name, {}).update({"fp32_perturbed_outer": sp}))
+            print(name, sp, flush=True)
+    elif args and args[0] == "--tol-sweep":
+        tol_sweep(args[1], [float(t) for t in args[2:]])
     else:
         main(args or ["small"])
