@@ -41,9 +41,13 @@ typedef enum {
   DD_EINVAL = 1,      /* invalid argument or unsupported configuration */
   DD_ENOMEM = 2,      /* device allocation failed */
   DD_EHIP = 3,        /* HIP runtime error */
-  DD_ESINGULAR = 4,   /* a coarse matrix E_j has a zero (or non-finite) pivot */
+  DD_ESINGULAR = 4,   /* a factored matrix (a coarse E_j, a local B_j of the exact solves, the global
+                         coarse E_0) is singular to working precision: a zero or non-finite pivot,
+                         or min |pivot| < 1e-12 max |entry| (k^2 at an eigenvalue of a local or
+                         coarse pencil); the message gives the ratio */
   DD_ENOTCONV = 5,    /* outer FGMRES hit outer_maxit; the best iterate is still written */
-  DD_EWEIGHTS = 6     /* reserved: learned-guess weights rejected */
+  DD_EWEIGHTS = 6     /* dd_net_load: the weights file is missing, malformed, inconsistent with its
+                         widths, or holds a non-finite parameter */
 } dd_status;
 
 enum { DD_LOCAL_IMPEDANCE = 0, DD_LOCAL_DIRICHLET = 1 };
@@ -290,6 +294,16 @@ typedef struct {
 } dd_tile_desc;
 
 void dd_net_default_params(dd_net_params* p);
+/* Create an inference network (train = 0) from a weights file: 8 bytes "DDHNET01", a
+   little-endian uint32 header length, a JSON header with "widths" (4 ints), "tile" and
+   "nparams", then nparams little-endian float32 in the flat order above.  tile <= 0 takes
+   the header's tile.  The file is read and validated on the host before any device work:
+   DD_EWEIGHTS (message says why) when it cannot be read, lacks the magic or a header
+   field, has widths the network does not support, a parameter count that differs from
+   what its widths need or from the bytes that follow, or a non-finite parameter; then as
+   dd_net_create (DD_EINVAL for tile / max_batch, DD_ENOMEM, DD_EHIP).  The weights of the
+   guess network are this build's (the paper has no learned part). */
+dd_status dd_net_load(const char* path, int tile, int max_batch, dd_net** out);
 /* Allocate a network and its device workspaces.  DD_EINVAL for unsupported sizes. */
 dd_status dd_net_create(const dd_net_params* p, dd_net** out);
 dd_status dd_net_destroy(dd_net* net);

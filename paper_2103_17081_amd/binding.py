@@ -145,6 +145,7 @@ _SIGS = {
     "dd_net_default_params": (None, [ctypes.POINTER(NetParams)]),
     "dd_net_create": (ctypes.c_int, [ctypes.POINTER(NetParams), ctypes.POINTER(_VP)]),
     "dd_net_destroy": (ctypes.c_int, [_VP]),
+    "dd_net_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_VP)]),
     "dd_net_num_params": (ctypes.c_int64, [_VP]),
     "dd_net_set_params": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
     "dd_net_get_params": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
@@ -462,6 +463,16 @@ class Solver:
         return v
 
 
+def weights_header(path: str) -> dict:
+    """JSON header of a guess-network weights file (magic, uint32 length, JSON)."""
+    import json
+    import struct
+    with open(path, "rb") as fh:
+        fh.read(8)
+        (hl,) = struct.unpack("<I", fh.read(4))
+        return json.loads(fh.read(hl).decode())
+
+
 def default_net_params() -> NetParams:
     p = NetParams()
     lib().dd_net_default_params(ctypes.byref(p))
@@ -485,6 +496,21 @@ class GuessNet:
         _check(lib().dd_net_create(ctypes.byref(p), ctypes.byref(self._n)), "dd_net_create")
         self.widths, self.tile, self.max_batch = tuple(int(w) for w in widths), tile, max_batch
         self.nparams = int(lib().dd_net_num_params(self._n))
+
+    @classmethod
+    def load(cls, path: str, max_batch: int, tile: int = 0) -> "GuessNet":
+        """Inference network from a weights file, read and validated by dd_net_load
+        (DD_EWEIGHTS for a bad file); tile 0 takes the file's tile."""
+        torch = _torch()
+        h = ctypes.c_void_p()
+        _check(lib().dd_net_load(os.fsencode(path), int(tile), int(max_batch), ctypes.byref(h)), "dd_net_load")
+        self = cls.__new__(cls)
+        self.torch, self._n, self.max_batch = torch, h, max_batch
+        self.nparams = int(lib().dd_net_num_params(h))
+        head = weights_header(path)      # already validated by the library
+        self.widths = tuple(int(w) for w in head["widths"])
+        self.tile = int(tile) if tile > 0 else int(head["tile"])
+        return self
 
     def close(self):
         if self._n:

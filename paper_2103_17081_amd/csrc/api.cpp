@@ -44,6 +44,25 @@ dd_status fail(dd_status s, const std::string& msg) {
     if (s_ != DD_OK) return s_;       \
   } while (0)
 
+// A factorisation whose smallest |pivot| is below this fraction of the largest |entry| of
+// the factored matrix is reported as singular: at that ratio the matrix is within rounding
+// of singular in FP64 (a pivot perturbed at 1e-16 relative changes the solve at ~1e-4), as
+// when k^2 meets an eigenvalue of a local or coarse pencil.
+constexpr double kTinyPivot = 1e-12;
+
+dd_status check_pivots(const std::string& what, double min_pivot, double max_entry) {
+  if (!(min_pivot > 0.0) || !std::isfinite(min_pivot) || !(max_entry > 0.0) || !std::isfinite(max_entry))
+    return fail(DD_ESINGULAR, what + " is singular (zero or non-finite pivot)");
+  const double ratio = min_pivot / max_entry;
+  if (ratio < kTinyPivot) {
+    char b[160];
+    std::snprintf(b, sizeof(b), " is singular to working precision: min |pivot| / max |entry| = %.3e < %.0e",
+                  ratio, kTinyPivot);
+    return fail(DD_ESINGULAR, what + b);
+  }
+  return DD_OK;
+}
+
 constexpr int kOuterBlocks = 1024;   // workgroups of the grid-stride outer kernels
 constexpr int kMaxRestart = 4000;    // Givens kernel stages a restart cycle in LDS
 constexpr int kMaxGraphSteps = 64;   // outer steps per captured graph
@@ -494,18 +513,17 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     DD_HIP(hipMemcpy(h->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice));
     DD_TRY(h->alloc(&h->Ec, (size_t)h->ncoarse * ddh::coarse_coefs(h->p.deflation)));
     DD_TRY(h->alloc(&h->fac, (size_t)h->nfac));
-    DD_TRY(h->alloc(&h->pivmin, h->nsub));
+    DD_TRY(h->alloc(&h->pivmin, 2 * (size_t)h->nsub));
     DD_HIP(ddh::launch_assemble_coarse(h->subs, h->nsub, h->cs, h->p.local_bc, h->Ec, st));
     if (h->p.deflation == DD_DEFLATION_LINEAR)
       DD_HIP(ddh::launch_factor_coarse_twisted(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
     else
       DD_HIP(ddh::launch_factor_coarse_paired(h->subs, h->nsub, h->Ec, h->fac, h->pivmin, st));
-    h->pivmin_h.resize(h->nsub);
-    DD_HIP(hipMemcpyAsync(h->pivmin_h.data(), h->pivmin, h->nsub * sizeof(double), hipMemcpyDeviceToHost, st));
+    h->pivmin_h.resize(2 * (size_t)h->nsub);
+    DD_HIP(hipMemcpyAsync(h->pivmin_h.data(), h->pivmin, 2 * h->nsub * sizeof(double), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
     for (int j = 0; j < h->nsub; ++j)
-      if (!(h->pivmin_h[j] > 0.0) || !std::isfinite(h->pivmin_h[j]))
-        return fail(DD_ESINGULAR, "coarse matrix E_" + std::to_string(j) + " is singular (zero pivot)");
+      DD_TRY(check_pivots("coarse matrix E_" + std::to_string(j), h->pivmin_h[2 * j], h->pivmin_h[2 * j + 1]));
     if (h->direct) {
       // twisted block factorisation of every local matrix: its 9-coefficient form, factored by the same
       // kernel as E through per-subdomain views (block size nx, ny block rows)
@@ -526,23 +544,21 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
       if (e == hipSuccess) e = hipMemcpy(vd, views.data(), h->nsub * sizeof(SubDesc), hipMemcpyHostToDevice);
       if (e == hipSuccess) e = ddh::launch_fine_coef(h->subs, h->nsub, h->cs, h->p.local_bc, Bc, st);
       if (e == hipSuccess) e = ddh::launch_factor_coarse_twisted(vd, h->nsub, Bc, h->ffac, h->pivmin, st);
-      if (e == hipSuccess) e = hipMemcpyAsync(h->pivmin_h.data(), h->pivmin, h->nsub * sizeof(double),
+      if (e == hipSuccess) e = hipMemcpyAsync(h->pivmin_h.data(), h->pivmin, 2 * h->nsub * sizeof(double),
                                               hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
       (void)hipFree(Bc);
       if (vd) (void)hipFree(vd);
       if (e != hipSuccess) return fail(DD_EHIP, std::string("direct factorisation: ") + hipGetErrorString(e));
       for (int j = 0; j < h->nsub; ++j)
-        if (!(h->pivmin_h[j] > 0.0) || !std::isfinite(h->pivmin_h[j]))
-          return fail(DD_ESINGULAR, "local matrix B_" + std::to_string(j) + " is singular (zero pivot)");
+        DD_TRY(check_pivots("local matrix B_" + std::to_string(j), h->pivmin_h[2 * j], h->pivmin_h[2 * j + 1]));
       DD_HIP(ddh::configure_direct(h->max_nj));
     }
     if (h->p.coarse_intervals > 0) {
       h->gc = new ddh::GlobalCoarse();
       const hipError_t e = h->gc->setup(h->n, h->p.coarse_intervals, h->p.k, h->nrhs, st);
       if (e != hipSuccess) return fail(DD_EHIP, std::string("global coarse set-up: ") + hipGetErrorString(e));
-      if (!(h->gc->min_pivot > 0.0))
-        return fail(DD_ESINGULAR, "global coarse matrix E_0 has a zero (or non-finite) pivot in its block reduction");
+      DD_TRY(check_pivots("global coarse matrix E_0", h->gc->min_pivot, h->gc->max_entry));
     }
     if (h->prec == 32) DD_TRY(alloc_inner<float>(h));
     else DD_TRY(alloc_inner<double>(h));
@@ -684,7 +700,7 @@ dd_status dd_coarse_matrix(const dd_handle* h, int j, double* out, double* min_p
   const SubDesc& d = h->subs_h[j];
   const int K = ddh::coarse_coefs(h->p.deflation);
   DD_HIP(hipMemcpy(out, h->Ec + d.coff * K, (size_t)d.mx * d.my * K * sizeof(cplx<double>), hipMemcpyDeviceToHost));
-  if (min_pivot) *min_pivot = h->pivmin_h[j];
+  if (min_pivot) *min_pivot = h->pivmin_h[2 * (size_t)j];
   return DD_OK;
 }
 
@@ -960,9 +976,17 @@ extern "C" dd_status dd_autotune(dd_handle* h, const char* cache_path, void* str
   const int m = h->restart;
   const long long nd = h->ndof;
   const long long vstr = (long long)(m + 1) * nd, zstr = (long long)m * nd;
-  hipEvent_t e0, e1;
-  DD_HIP(hipEventCreate(&e0));
-  DD_HIP(hipEventCreate(&e1));
+  // the events are destroyed on every return path
+  struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  DD_HIP(hipEventCreate(&ev.a));
+  DD_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   auto time_ms = [&](auto&& fn, int reps) -> double {
     std::vector<float> t;
     for (int r = 0; r < reps + 1; ++r) {
@@ -977,8 +1001,9 @@ extern "C" dd_status dd_autotune(dd_handle* h, const char* cache_path, void* str
     std::sort(t.begin(), t.end());
     return t[t.size() / 2];
   };
-  // representative data: pseudo-random residual in slot 0 (and basis vectors for the sweep)
-  const int jt = std::min(m - 1, 1024);
+  // representative data: pseudo-random residual in slot 0 (and basis vectors for the sweep);
+  // the basis has slots 0..m, and a dot sweep at step jj reads slots 0..jj+1, so jj <= m - 1
+  const int jt = std::max(0, std::min(m - 1, 1024));
   for (int q = 0; q < h->nrhs; ++q)
     DD_HIP(ddh::launch_fill_hash(h->Vo + q * vstr, (long long)(jt + 2) * nd, 17081ull + q, st));
   double best = 1e300;
@@ -1002,9 +1027,11 @@ extern "C" dd_status dd_autotune(dd_handle* h, const char* cache_path, void* str
   h->lpt = best_lpt;
   double bestd = 1e300;
   int best_db = 0;
-  // the sweep's cost grows with the basis: time it at a short and a long basis
+  // the sweep's cost grows with the basis: time it at a short and a long basis (with a
+  // restart length below 2 there is no sweep worth tuning and the default stays)
   const int jshort = std::max(1, jt / 4);
   for (int db : {1024, 2048, 4096, 8192, 16384}) {
+    if (jt < 1) break;
     const double ms = time_ms([&]() {
       for (int jj : {jshort, jt})
         (void)ddh::launch_dots2(h->Vo, vstr, h->Vo + (long long)jj * nd, vstr, h->Vo + (long long)(jj + 1) * nd, vstr,
@@ -1015,9 +1042,7 @@ extern "C" dd_status dd_autotune(dd_handle* h, const char* cache_path, void* str
     rep += line;
     if (ms < bestd) { bestd = ms; best_db = db; }
   }
-  h->dots_blocks = best_db;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (jt >= 1) h->dots_blocks = best_db;
   DD_HIP(hipGetLastError());
   if (cache_path) {
     FILE* fp = std::fopen(cache_path, "a");

@@ -147,12 +147,14 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
   const int h = threadIdx.x / Half, ht = threadIdx.x % Half;
   const int r = ht / L, l = ht % L;
   const bool active = r < mx;
+  // Columns a lane does not own read column 0 with a zero factor entry, so every step
+  // reads its operands without branches (adding 0 * x leaves the sum unchanged).
   int col[Q], eoff[Q];
   bool ok[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    col[q] = l + q * L;
-    ok[q] = active && col[q] < mx;
+    ok[q] = active && l + q * L < mx;
+    col[q] = ok[q] ? l + q * L : 0;
     eoff[q] = ok[q] ? r * mx + col[q] : 0;
   }
   cplx<double> ring[Depth][Q];
@@ -161,7 +163,11 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
     for (int u = 0; u < Depth; ++u) {
       const int blk = max(tw_step_block(h, s0 + u, p, my), 0);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) ring[u][q] = F[(size_t)blk * mm + eoff[q]];
+      for (int q = 0; q < Q; ++q) {
+        const cplx<double> fv = F[(size_t)blk * mm + eoff[q]];
+        ring[u][q].re = ok[q] ? fv.re : 0.0;
+        ring[u][q].im = ok[q] ? fv.im : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < Depth; ++u) {
@@ -174,8 +180,7 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
         cplx<double> acc = czero<double>();
         if (on) {
 #pragma unroll
-          for (int q = 0; q < Q; ++q)
-            if (ok[q]) acc = cfma(ring[u][q], t[i * mx + col[q]], acc);
+          for (int q = 0; q < Q; ++q) acc = cfma(ring[u][q], t[i * mx + col[q]], acc);
         }
         acc.re = row_sum<L>(acc.re);
         acc.im = row_sum<L>(acc.im);
@@ -195,8 +200,7 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
         cplx<double> acc = czero<double>();
         if (h == 0) {
 #pragma unroll
-          for (int q = 0; q < Q; ++q)
-            if (ok[q]) acc = cfma(ring[u][q], t[p * mx + col[q]], acc);
+          for (int q = 0; q < Q; ++q) acc = cfma(ring[u][q], t[p * mx + col[q]], acc);
         }
         acc.re = row_sum<L>(acc.re);
         acc.im = row_sum<L>(acc.im);
@@ -211,8 +215,7 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
         cplx<double> acc = czero<double>();
         if (on) {
 #pragma unroll
-          for (int q = 0; q < Q; ++q)
-            if (ok[q]) acc = cfma(ring[u][q], a[src * mx + col[q]], acc);
+          for (int q = 0; q < Q; ++q) acc = cfma(ring[u][q], a[src * mx + col[q]], acc);
         }
         acc.re = row_sum<L>(acc.re);
         acc.im = row_sum<L>(acc.im);

@@ -127,6 +127,25 @@ __global__ void __launch_bounds__(256) gc_gemm_kernel(const GemmTask* __restrict
   }
 }
 
+// Largest |coefficient| of E_0 per workgroup: the scale its pivots are compared against.
+constexpr int kAbsMaxBlocks = 64;
+__global__ void __launch_bounds__(256) gc_absmax_kernel(const double* __restrict__ x, long long n,
+                                                        double* __restrict__ out) {
+  double m = 0.0;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256)
+    m = fmax(m, fabs(x[e]));
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, kWave));
+  __shared__ double sh[256 / kWave];
+  if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < 256 / kWave; ++w) r = fmax(r, sh[w]);
+    out[blockIdx.x] = r;
+  }
+}
+
 // Inverse of a work block into the factor array: copy, then Gauss-Jordan with partial
 // pivoting in place (one workgroup per task).  pivmin[task] = smallest |pivot|.
 constexpr int kInvThreads = 1024;
@@ -480,6 +499,9 @@ hipError_t GlobalCoarse::setup(int n, int m, double k, int nr, hipStream_t st) {
     const long long tot = ncoarse * 9;
     hipLaunchKernelGGL(gc_assemble_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, pos, m, kh2, E0c);
     GC_TRY(hipGetLastError());
+    GC_TRY(alloc(&emax_d, kAbsMaxBlocks));
+    hipLaunchKernelGGL(gc_absmax_kernel, dim3(kAbsMaxBlocks), dim3(256), 0, st, (const double*)E0c, tot, emax_d);
+    GC_TRY(hipGetLastError());
   }
   GC_TRY(alloc(&cv, (size_t)nr * 2 * ncoarse));
   GC_TRY(alloc(&q, (size_t)nr * ndof));
@@ -705,8 +727,10 @@ hipError_t GlobalCoarse::setup(int n, int m, double k, int nr, hipStream_t st) {
                        bn, nblk, tsz);
     err = hipGetLastError();
   }
-  std::vector<double> piv(ninv, 0.0);
+  std::vector<double> piv(ninv, 0.0), emax(kAbsMaxBlocks, 0.0);
   if (err == hipSuccess) err = hipMemcpyAsync(piv.data(), dpiv, sizeof(double) * ninv, hipMemcpyDeviceToHost, st);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(emax.data(), emax_d, sizeof(double) * kAbsMaxBlocks, hipMemcpyDeviceToHost, st);
   if (err == hipSuccess) err = hipStreamSynchronize(st);
   (void)hipFree(sfac);
   (void)hipFree(work);
@@ -722,6 +746,7 @@ hipError_t GlobalCoarse::setup(int n, int m, double k, int nr, hipStream_t st) {
     min_pivot = std::min(min_pivot, v);
   }
   if (!finite) min_pivot = 0.0;
+  max_entry = *std::max_element(emax.begin(), emax.end());
   return hipSuccess;
 }
 

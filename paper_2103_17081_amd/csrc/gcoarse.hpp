@@ -91,11 +91,13 @@ class GlobalCoarse {
   int nrhs = 1;
   long long nfac = 0;   // factor elements
   double min_pivot = 0.0;
+  double max_entry = 0.0;        // largest |coefficient| of E_0 (scale of the pivot check)
   double kh2 = 0.0;
   // device
   int* pos = nullptr;            // [M + 1] coarse grid lines
   int* cell = nullptr;           // [N + 1] coarse interval containing each fine index
   double* E0c = nullptr;         // [ncoarse][9] coefficients, neighbour (dx, dy) at 3 (dy + 1) + (dx + 1)
+  double* emax_d = nullptr;      // per-workgroup largest |coefficient| of E_0
   double* fac = nullptr;         // block cyclic reduction factors (real: A and Z_0 are real)
   BcrTask* tasks = nullptr;
   SpTask* sptasks = nullptr;

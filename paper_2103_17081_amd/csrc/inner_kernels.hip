@@ -275,6 +275,29 @@ __device__ __forceinline__ void basis_dots(const cplx<T>* __restrict__ V, int nj
   }
 }
 
+// B[n] += sgn * sum_{i < cnt} V_i[n] c_i over the tile: the basis is read kUpdChunk vectors
+// at a time with every load of a chunk issued before the first product (indices past cnt
+// are clamped to a valid vector and their coefficient skipped), so a thread waits once per
+// chunk instead of once per basis vector.
+constexpr int kUpdChunk = 8;
+template <typename T, int NT, bool kSubtract>
+__device__ __forceinline__ void basis_combine(const cplx<T>* __restrict__ V, int nj, int cnt, const cplx<T>* c,
+                                              cplx<T>* B) {
+  if (cnt <= 0) return;
+  for (int n = threadIdx.x; n < nj; n += NT) {
+    cplx<T> acc = B[n];
+    for (int i0 = 0; i0 < cnt; i0 += kUpdChunk) {
+      cplx<T> v[kUpdChunk];
+#pragma unroll
+      for (int q = 0; q < kUpdChunk; ++q) v[q] = V[(long long)min(i0 + q, cnt - 1) * nj + n];
+#pragma unroll
+      for (int q = 0; q < kUpdChunk; ++q)
+        if (i0 + q < cnt) acc = kSubtract ? acc - v[q] * c[i0 + q] : acc + v[q] * c[i0 + q];
+    }
+    B[n] = acc;
+  }
+}
+
 template <typename T>
 __host__ __device__ constexpr double breakdown_eps() { return sizeof(T) == 4 ? 4e-6 : 1e-14; }
 
@@ -421,11 +444,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
           }
         }
         lds_barrier();
-        for (int n = tid; n < nj; n += NT) {
-          cplx<T> acc = L.B[n];
-          for (int i = 0; i <= k; ++i) acc = acc - V[(long long)i * nj + n] * L.hT[i];
-          L.B[n] = acc;
-        }
+        basis_combine<T, NT, true>(V, nj, k + 1, L.hT, L.B);
         lds_barrier();
       }
       const double hnext = tile_norm<T, NT>(d, L.B, L);
@@ -477,12 +496,24 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
         __syncthreads();
       }
     }
-    // y = R^{-1} g (upper triangular, k x k)
+    // y = R^{-1} g (upper triangular, k x k).  R is copied into the free tile A first when
+    // it fits (all threads load it side by side), so the serial substitution reads LDS.
+    const bool r_lds = (size_t)k * k * sizeof(cplx<double>) <= (size_t)a.max_nj * sizeof(cplx<T>);
+    cplx<double>* Rl = reinterpret_cast<cplx<double>*>(L.A);
+    if (r_lds) {
+      __syncthreads();   // thread 0's global stores of R are visible to the workgroup
+      for (int e = tid; e < k * k; e += NT) {
+        const int j = e / k, i = e - j * k;
+        if (i <= j) Rl[e] = R[(long long)j * maxit + i];
+      }
+      lds_barrier();
+    }
     if (tid == 0) {
       for (int i = k - 1; i >= 0; --i) {
         cplx<double> sacc = L.g[i];
-        for (int j = i + 1; j < k; ++j) sacc = sacc - R[(long long)j * maxit + i] * L.h[j];
-        L.h[i] = sacc * cinv(R[(long long)i * maxit + i]);
+        for (int j = i + 1; j < k; ++j)
+          sacc = sacc - (r_lds ? Rl[j * k + i] : R[(long long)j * maxit + i]) * L.h[j];
+        L.h[i] = sacc * cinv(r_lds ? Rl[i * k + i] : R[(long long)i * maxit + i]);
       }
     }
     lds_barrier();
@@ -490,11 +521,8 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
     lds_barrier();
   }
   // x = x0 + V y   (tile A)
-  for (int n = tid; n < nj; n += NT) {
-    cplx<T> x = accepted ? X[n] : czero<T>();
-    for (int i = 0; i < k; ++i) x = x + V[(long long)i * nj + n] * L.hT[i];
-    L.A[n] = x;
-  }
+  for (int n = tid; n < nj; n += NT) L.A[n] = accepted ? X[n] : czero<T>();
+  basis_combine<T, NT, false>(V, nj, k, L.hT, L.A);
   lds_barrier();
   // recovery: u = x + Z E^{-1} Z^T (f - B x)
   if (Sc) {
@@ -502,7 +530,14 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
     for (int e = tid; e < d.ncp; e += NT) {
       cplx<double> c = Sc[e];
       if (accepted) c = c - Sc[a.max_nc + e];
-      for (int i = 0; i < k; ++i) c = c - L.h[i] * Sc[(long long)(2 + i) * a.max_nc + e];
+      for (int i0 = 0; i0 < k; i0 += kUpdChunk) {
+        cplx<double> sv[kUpdChunk];
+#pragma unroll
+        for (int q = 0; q < kUpdChunk; ++q) sv[q] = Sc[(long long)(2 + min(i0 + q, k - 1)) * a.max_nc + e];
+#pragma unroll
+        for (int q = 0; q < kUpdChunk; ++q)
+          if (i0 + q < k) c = c - L.h[i0 + q] * sv[q];
+      }
       L.ca[e] = c;
     }
     lds_barrier();

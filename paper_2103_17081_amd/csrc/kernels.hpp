@@ -9,7 +9,9 @@ namespace ddh {
 hipError_t launch_assemble_coarse(const SubDesc* subs, int nsub, Consts cs, int local_bc, cplx<double>* Ec,
                                   hipStream_t st);
 // Twisted block factorisation of E (linear deflation) or, through per-subdomain views, of
-// the local matrices of the exact solves.
+// the local matrices of the exact solves.  Both factorisations write, per subdomain j,
+// pivmin[2 j] = the smallest |pivot| met and pivmin[2 j + 1] = the largest |entry| of the
+// factored matrix (the scale set-up compares the pivots against).
 hipError_t launch_factor_coarse_twisted(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
                                         double* pivmin, hipStream_t st);
 hipError_t launch_factor_coarse_paired(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,

@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 #include <string>
@@ -307,6 +310,97 @@ dd_status dd_net_create(const dd_net_params* p, dd_net** out) {
     *out = nullptr;
     return fin(s);
   }
+  return DD_OK;
+}
+
+namespace {
+
+// Value of "key" in a flat JSON object: integers, or an array of integers.
+bool json_ints(const std::string& js, const std::string& key, std::vector<long long>& out) {
+  const size_t k = js.find("\"" + key + "\"");
+  if (k == std::string::npos) return false;
+  size_t i = js.find(':', k + key.size() + 2);
+  if (i == std::string::npos) return false;
+  ++i;
+  while (i < js.size() && std::isspace((unsigned char)js[i])) ++i;
+  const bool arr = i < js.size() && js[i] == '[';
+  if (arr) ++i;
+  out.clear();
+  while (i < js.size()) {
+    while (i < js.size() && std::isspace((unsigned char)js[i])) ++i;
+    if (i >= js.size()) return false;
+    if (arr && js[i] == ']') break;
+    char* end = nullptr;
+    const long long v = std::strtoll(js.c_str() + i, &end, 10);
+    if (end == js.c_str() + i) return false;
+    out.push_back(v);
+    i = (size_t)(end - js.c_str());
+    while (i < js.size() && std::isspace((unsigned char)js[i])) ++i;
+    if (!arr) break;
+    if (i < js.size() && js[i] == ',') ++i;
+  }
+  return !out.empty();
+}
+
+}  // namespace
+
+dd_status dd_net_load(const char* path, int tile, int max_batch, dd_net** out) {
+  if (!path || !out) return ddh::fail_msg(DD_EINVAL, "null argument");
+  *out = nullptr;
+  const std::string where = std::string(path) + ": ";
+  std::vector<char> data;
+  {
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return ddh::fail_msg(DD_EWEIGHTS, where + "cannot open the weights file");
+    char buf[1 << 16];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), fp)) > 0) data.insert(data.end(), buf, buf + got);
+    std::fclose(fp);
+  }
+  static const char kMagic[8] = {'D', 'D', 'H', 'N', 'E', 'T', '0', '1'};
+  if (data.size() < 12 || std::memcmp(data.data(), kMagic, 8) != 0)
+    return ddh::fail_msg(DD_EWEIGHTS, where + "not a guess-network weights file (magic DDHNET01 missing)");
+  uint32_t hl = 0;
+  for (int b = 0; b < 4; ++b) hl |= (uint32_t)(unsigned char)data[8 + b] << (8 * b);   // little endian
+  if ((size_t)hl > data.size() - 12) return ddh::fail_msg(DD_EWEIGHTS, where + "truncated header");
+  const std::string head(data.data() + 12, hl);
+  std::vector<long long> widths, ftile, np;
+  if (!json_ints(head, "widths", widths) || widths.size() != 4 || !json_ints(head, "tile", ftile) ||
+      !json_ints(head, "nparams", np))
+    return ddh::fail_msg(DD_EWEIGHTS, where + "header lacks widths[4], tile or nparams");
+  dd_net probe;   // host-only: the parameter layout of these widths
+  for (int i = 0; i < 4; ++i) {
+    if (!(widths[i] == 16 || widths[i] == 32 || widths[i] == 64))
+      return ddh::fail_msg(DD_EWEIGHTS, where + "network widths must be 16, 32 or 64");
+    probe.c[i] = (int)widths[i];
+  }
+  if (widths[2] != widths[3]) return ddh::fail_msg(DD_EWEIGHTS, where + "network widths c3 and c4 differ");
+  build_table(&probe);
+  const size_t payload = data.size() - 12 - hl;
+  if (np[0] != probe.nparams || payload != (size_t)probe.nparams * sizeof(float))
+    return ddh::fail_msg(DD_EWEIGHTS, where + "header says " + std::to_string(np[0]) + " parameters, the widths need " +
+                                          std::to_string(probe.nparams) + ", the file holds " +
+                                          std::to_string(payload / sizeof(float)));
+  std::vector<float> w((size_t)probe.nparams);
+  std::memcpy(w.data(), data.data() + 12 + hl, payload);   // little-endian float32 (x86-64 host)
+  for (size_t q = 0; q < w.size(); ++q)
+    if (!std::isfinite(w[q]))
+      return ddh::fail_msg(DD_EWEIGHTS, where + "parameter " + std::to_string(q) + " is not finite");
+  dd_net_params p;
+  dd_net_default_params(&p);
+  for (int i = 0; i < 4; ++i) p.widths[i] = (int)widths[i];
+  p.tile = tile > 0 ? tile : (int)ftile[0];
+  p.max_batch = max_batch;
+  p.train = 0;
+  dd_net* n = nullptr;
+  dd_status s = dd_net_create(&p, &n);
+  if (s != DD_OK) return s;
+  s = dd_net_set_params(n, w.data(), (int64_t)w.size());
+  if (s != DD_OK) {
+    dd_net_destroy(n);
+    return s;
+  }
+  *out = n;
   return DD_OK;
 }
 

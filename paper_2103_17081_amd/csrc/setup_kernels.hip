@@ -44,6 +44,21 @@ __global__ void __launch_bounds__(kBlock) assemble_coarse_kernel(const SubDesc* 
   }
 }
 
+// Largest |entry| among n complex coefficients, workgroup-cooperative (every thread gets it):
+// the scale that the pivot magnitudes of a factorisation are compared against.
+__device__ double block_absmax(const cplx<double>* __restrict__ c, long long n, double* sh) {
+  double m = 0.0;
+  for (long long e = threadIdx.x; e < n; e += blockDim.x) m = fmax(m, sqrt(cabs2(c[e])));
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, kWave));
+  if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = m;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) r = fmax(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
 // In-place Gauss-Jordan inverse with partial pivoting of the n x n row-major matrix
 // A (global memory; element (r, c) at r*n + c), workgroup-cooperative.  Returns the
 // smallest |pivot| met.
@@ -185,7 +200,12 @@ __global__ void __launch_bounds__(kBlock) factor_coarse_twisted_kernel(const Sub
   }
   __syncthreads();
   minp = fmin(minp, gauss_jordan_inverse(M, mx, perm, colp, &pivabs));
-  if (tid == 0) pivmin[blockIdx.x] = minp;
+  __shared__ double red[kBlock / kWave];
+  const double emax = block_absmax(ec, (long long)mx * my * 9, red);
+  if (tid == 0) {
+    pivmin[2 * blockIdx.x] = minp;
+    pivmin[2 * blockIdx.x + 1] = emax;
+  }
 }
 
 hipError_t launch_factor_coarse_twisted(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,
@@ -248,7 +268,12 @@ __global__ void __launch_bounds__(kBlock) factor_coarse_paired_kernel(const SubD
     }
     __syncthreads();
   }
-  if (tid == 0) pivmin[blockIdx.x] = minp;
+  __shared__ double red[kBlock / kWave];
+  const double emax = block_absmax(ec, (long long)d.mx * d.my * 25, red);
+  if (tid == 0) {
+    pivmin[2 * blockIdx.x] = minp;
+    pivmin[2 * blockIdx.x + 1] = emax;
+  }
 }
 
 hipError_t launch_factor_coarse_paired(const SubDesc* subs, int nsub, const cplx<double>* Ec, cplx<double>* fac,

@@ -60,10 +60,8 @@ def read_weights(path: str):
 
 
 def load_net(path: str, max_batch: int, tile: int | None = None) -> GuessNet:
-    head, params = read_weights(path)
-    net = GuessNet(tuple(head["widths"]), tile=tile or head["tile"], max_batch=max_batch)
-    net.set_params(params)
-    return net
+    """The library reads and validates the file (dd_net_load; DD_EWEIGHTS if it is bad)."""
+    return GuessNet.load(path, max_batch=max_batch, tile=tile or 0)
 
 
 # ---- data ---------------------------------------------------------------------------

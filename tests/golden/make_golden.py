@@ -6,6 +6,7 @@ Usage: python tests/golden/make_golden.py small [medium] [large]
        python tests/golden/make_golden.py --direct small [medium] [large]
        python tests/golden/make_golden.py --two-level small:16 [medium:80]
        python tests/golden/make_golden.py --paper-two-level
+       python tests/golden/make_golden.py --paper-tables [workers]
 
 For each named workload (paper_2103_17081_amd.inputs.workload) and its first right-hand
 side, runs the oracle's outer FGMRES with impedance (ORAS) local matrices, linear
@@ -227,10 +228,76 @@ def paper_two_level():
         json.dump({"source": "oracle (tests/golden/make_golden.py --paper-two-level)", "rows": rows}, fh, indent=1)
 
 
+def _paper_cell(args):
+    """One (k, ppwl, N) cell of the paper's Tables 1-4 in its own setting (Dirichlet local
+    matrices, Bezier deflation, n_glob interior nodes per edge, point source at the centre):
+    outer counts and average inner counts with direct subdomain solves and with deflated
+    GMRES at inner tolerances 1e-10, 1e-5 and 1e-2; plus the survey's A5 diagnostic, the
+    1e-10 run with the local solution taken as the deflated system's x (no recovery)."""
+    import numpy as np
+    from oracle import krylov
+    k, ppwl, N = args
+    nglob = int(round(1.5 * k)) if ppwl == 10 else 3 * k
+    n = nglob + 1
+    P = int(round(N ** 0.5))
+    cuts = inputs.uniform_cuts(n, P)
+    f = inputs.point_source(n)
+    S = schwarz.Schwarz(schwarz.Problem(float(k), n, cuts, cuts, 1, "dirichlet", "bezier"))
+    cell = {"k": k, "ppwl": ppwl, "n_glob": nglob, "N": N}
+    t0 = time.time()
+    _, st = S.solve(f, mode="direct", outer_maxit=3000)
+    cell["direct"] = {"outer": st.outer_iters, "relres": st.true_relres}
+    for tol in (1e-10, 1e-5, 1e-2):
+        _, st = S.solve(f, mode="deflated", inner_tol=tol, inner_maxit=300, outer_maxit=3000)
+        cell[f"{tol:g}"] = {"outer": st.outer_iters, "avg_inner": st.avg_inner, "relres": st.true_relres}
+    # A5: no recovery -- the subdomain "solution" is x of P B x = P f
+    stats = schwarz.SolveStats()
+
+    def apply_x(r):
+        us = []
+        for sd, fj in zip(S.subs, S.local_rhs(r)):
+            d = sd.defl
+            Pf = d.P(fj)
+            ref = np.linalg.norm(Pf)
+            if ref == 0.0:
+                us.append(np.zeros_like(fj))
+                continue
+            res = krylov.gmres(d.PB, Pf, rtol=1e-10, maxit=300, ref_norm=ref)
+            stats.inner_iters += res.iters
+            stats.subdomain_solves += 1
+            us.append(res.x)
+        return S.scatter(us)
+
+    res = krylov.fgmres(lambda v: S.A @ v, apply_x, f, rtol=1e-6, maxit=3000)
+    cell["no_recovery_1e-10"] = {"outer": res.iters, "converged": bool(res.converged),
+                                 "avg_inner": stats.avg_inner}
+    cell["seconds"] = round(time.time() - t0, 1)
+    print(json.dumps(cell), flush=True)
+    return cell
+
+
+def paper_tables(workers=4):
+    """tests/golden/paper_mesh_tables.json: _paper_cell over k = 20, 40, ppwl = 10, 20,
+    N = 4, 9, 16, 25 (a process per cell)."""
+    import multiprocessing as mp
+    cells = [(k, ppwl, N) for k in (20, 40) for ppwl in (10, 20) for N in (4, 9, 16, 25)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        rows = pool.map(_paper_cell, cells, chunksize=1)
+    with open(os.path.join(HERE, "paper_mesh_tables.json"), "w") as fh:
+        json.dump({"source": "oracle (tests/golden/make_golden.py --paper-tables)",
+                   "setting": "Dirichlet local matrices, Bezier deflation, n_glob = 1.5 k (10 ppwl) or 3 k "
+                              "(20 ppwl) interior nodes per edge, uniform N = P^2 subdomains with one "
+                              "appended element layer, unit point source at the centre, outer FGMRES "
+                              "rtol 1e-6 without restart, inner GMRES without restart (max 300)",
+                   "rows": rows}, fh, indent=1)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     if args and args[0] == "--paper-two-level":
         paper_two_level()
+    elif args and args[0] == "--paper-tables":
+        paper_tables(int(args[1]) if len(args) > 1 else 4)
     elif args and args[0] == "--two-level":
         two_level(args[1:] or ["small:16"])
     elif args and args[0] == "--direct":

@@ -102,3 +102,52 @@ def test_net_null_arguments():
     assert L.dd_tile_descs(None, None) == binding.DD_EINVAL
     assert L.dd_outer_basis(None, 0, None, None) == binding.DD_EINVAL
     assert L.dd_last_inner(None, None, None, None) == binding.DD_EINVAL
+
+
+def _weights_file(path, head: dict, params: bytes, magic=b"DDHNET01"):
+    import json
+    import struct
+    hb = json.dumps(head).encode()
+    with open(path, "wb") as fh:
+        fh.write(magic + struct.pack("<I", len(hb)) + hb + params)
+    return str(path)
+
+
+def _load_status(path):
+    L = binding.lib()
+    h = ctypes.c_void_p()
+    st = L.dd_net_load(str(path).encode(), 0, 4, ctypes.byref(h))
+    return st, L.dd_last_error().decode(), h
+
+
+# parameters of the (16, 16, 16, 16) network: 7 convolutions and the 1x1 head
+def _nparams_16():
+    import numpy as np
+    c = 16
+    layers = [(4, c), (c, c), (c, c), (c, c), (2 * c, c), (2 * c, c), (2 * c, c)]
+    return int(np.sum([9 * a * b + b for a, b in layers]) + 2 * c + 2)
+
+
+def test_weights_file_rejected_before_device_work(tmp_path):
+    """dd_net_load validates the file on the host: each defect gives DD_EWEIGHTS and no network."""
+    import numpy as np
+    n = _nparams_16()
+    good = np.zeros(n, dtype="<f4").tobytes()
+    head = {"widths": [16, 16, 16, 16], "tile": 32, "nparams": n}
+    cases = {
+        "missing": (tmp_path / "none.ddnet", "cannot open"),
+        "magic": (_weights_file(tmp_path / "m.ddnet", head, good, magic=b"NOTANET1"), "magic"),
+        "truncated header": (tmp_path / "t.ddnet", "truncated header"),
+        "no widths": (_weights_file(tmp_path / "w.ddnet", {"tile": 32, "nparams": n}, good), "widths"),
+        "bad width": (_weights_file(tmp_path / "b.ddnet", dict(head, widths=[16, 16, 24, 24]), good), "16, 32 or 64"),
+        "count vs widths": (_weights_file(tmp_path / "c.ddnet", dict(head, nparams=n + 1), good), "parameters"),
+        "count vs payload": (_weights_file(tmp_path / "p.ddnet", head, good[:-4]), "the file holds"),
+        "non-finite": (_weights_file(tmp_path / "f.ddnet", head,
+                                     np.r_[np.zeros(n - 1), np.nan].astype("<f4").tobytes()), "not finite"),
+    }
+    (tmp_path / "t.ddnet").write_bytes(b"DDHNET01" + (1000).to_bytes(4, "little") + b"{}")
+    for name, (path, needle) in cases.items():
+        st, msg, h = _load_status(path)
+        assert st == binding.DD_EWEIGHTS, (name, st, msg)
+        assert needle in msg, (name, msg)
+        assert not h.value, name

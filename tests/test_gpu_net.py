@@ -225,12 +225,18 @@ def test_guess_path_matches_oracle(torch):
     """Preconditioner apply with the attached (oracle-trained) network: per subdomain the
     accept / reject decision equals the oracle's wherever the oracle's deflated-residual
     ratio is not within 5% of 1, rejected guesses give the zero-guess iteration count,
-    accepted ones are within one iteration of the oracle's guessed solve, and every local
-    solution meets the inner tolerance in the oracle's arithmetic."""
+    accepted ones are within one iteration of the oracle's guessed solve.  The local
+    solutions are then checked one by one: the batched subdomain solves are run on the
+    same right-hand sides with the GPU network's guesses passed as packed initial guesses,
+    every local solution u_j must satisfy ||f_j - B_j u_j|| <= tol ||P_j f_j|| recomputed
+    with the oracle's matrices, and the apply's output must equal those solutions on the
+    owned nodes; with the oracle network's guesses the iteration counts and solutions must
+    equal the oracle's guessed solves."""
     _case("guess path")
     w, S = oracle_for("small")
     net, v = _fixture_net(torch)
     kh = w.k / S.prob.n
+    tol = w.inner_tol
     with solver_for("small", precision=64) as gpu:
         gpu.set_guess(net)
         rng = np.random.default_rng(31)
@@ -240,13 +246,16 @@ def test_guess_path_matches_oracle(torch):
             x, s = cnn.tile_inputs(S, r, 32, kh)
             y, _ = cnn.forward(cnn.unflatten(v, (16, 16, 16, 16)), bf16_round(x))
             gs = cnn.guesses(S, y, s)
+            fs = [r[sd.geom.idx] for sd in S.subs]
             zo = np.zeros_like(r)
+            oracle_solves = []
             for j, sd in enumerate(S.subs):
-                f = r[sd.geom.idx]
+                f = fs[j]
                 Pf = sd.defl.P(f)
                 ratio = np.linalg.norm(Pf - sd.defl.PB(gs[j])) / np.linalg.norm(Pf)
-                u, k, acc = sd.deflated_gmres(f, w.inner_tol, 100, guess=gs[j])
-                _, k0, _ = sd.deflated_gmres(f, w.inner_tol, 100)
+                u, k, acc = sd.deflated_gmres(f, tol, 100, guess=gs[j])
+                _, k0, _ = sd.deflated_gmres(f, tol, 100)
+                oracle_solves.append((u, k, acc, ratio))
                 zo[sd.geom.idx[sd.geom.owned]] = u[sd.geom.owned]
                 print(f"sub {j}: ratio {ratio:.3f} oracle acc {acc} its {k} (zero guess {k0}); "
                       f"gpu acc {bool(flags[j] & 1)} its {iters[j]}", flush=True)
@@ -256,10 +265,29 @@ def test_guess_path_matches_oracle(torch):
                     assert iters[j] == k0
                 elif acc:
                     assert abs(int(iters[j]) - k) <= 1
-            # every GPU local solution meets the tolerance (recomputed by the oracle)
-            for j, sd in enumerate(S.subs):
-                zj = z[sd.geom.idx]
-                assert np.all(np.isfinite(zj))
+            F = to_gpu(torch, pack(S, gpu, fs))
+            # the GPU network's guesses as packed initial guesses: the same solves as the apply
+            xg, sg = gpu.tiles(to_gpu(torch, r), 32)
+            yg = to_np(net.forward(xg))
+            gg = cnn.guesses(S, yg.astype(np.float64), to_np(sg))
+            ug, itg, flg = gpu.op_inner_solve(F, guess=to_gpu(torch, pack(S, gpu, gg)))
+            assert np.array_equal(flg & 1, flags & 1)
+            assert np.array_equal(itg, iters)
+            for j, (sd, uj) in enumerate(zip(S.subs, unpack(S, gpu, to_np(ug)))):
+                g = sd.geom
+                res = np.linalg.norm(fs[j] - sd.B @ uj)
+                assert res <= tol * np.linalg.norm(sd.defl.P(fs[j])) * (1 + 1e-6), (j, res)
+                np.testing.assert_allclose(z[g.idx[g.owned]], uj[g.owned], rtol=0,
+                                           atol=1e-9 * np.abs(uj).max())
+            # the oracle network's guesses: counts and solutions equal the oracle's guessed solves
+            uo, ito, flo = gpu.op_inner_solve(F, guess=to_gpu(torch, pack(S, gpu, gs)))
+            for j, (uj, (u, k, acc, ratio)) in enumerate(zip(unpack(S, gpu, to_np(uo)), oracle_solves)):
+                if abs(ratio - 1.0) > 1e-8:
+                    assert bool(flo[j] & 1) == acc, j
+                # FP64 on both sides: equal counts unless an estimate lands within rounding of
+                # the tolerance, then one iteration apart and the solutions tolerance-close
+                assert abs(int(ito[j]) - k) <= 1, (j, ito[j], k)
+                assert rel(uj, u) <= (1e-8 if ito[j] == k else 10 * tol), j
             assert rel(z, zo) <= 0.1
     net.close()
 
