@@ -234,6 +234,23 @@ dd_status dd_op_scatter(dd_handle* h, int precision, const void* u, void* z, voi
 dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void* u, int32_t* iters,
                             int32_t* flags, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): dd_op_inner_solve without a guess, with
+   every scratch buffer of the subdomain solves -- Krylov bases, R factors, kept coarse
+   vectors, work tiles, per-solve counts and flags, counters -- taken from a static device
+   array of 64 MiB that each GPU holds from library load until the process ends, instead of
+   the handle's workspaces.  Calls nothing that allocates.  f (packed [nrhs][nfine], the
+   handle's inner precision) is read in place and must not change until the solves are done;
+   u as dd_op_inner_solve.  iters, flags: host int arrays of nsub * nrhs (may be NULL); when
+   both are NULL the call only enqueues work on `stream` (nothing synchronises, so it can be
+   captured), otherwise it copies them and synchronises.  Every call on one GPU shares the
+   array, which keeps the last call's contents (each call clears the counters it needs):
+   calls that overlap on one GPU race.  DD_EINVAL for exact local solves or the multi-launch
+   form, or when the handle's solves need more than 64 MiB of scratch (the message gives the
+   size; it grows with nrhs * nfine * inner_maxit). */
+dd_status dd_op_inner_solve_static(dd_handle* h, const void* f, void* u, int32_t* iters, int32_t* flags,
+                                   void* stream);
+
 /* ---- two-level method (coarse_intervals > 0) ---------------------------------------- */
 
 /* Coarse unknowns (M - 1)^2 of the global coarse space, 0 for the one-level method. */

@@ -142,6 +142,8 @@ _SIGS = {
     "dd_op_scatter": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "dd_op_inner_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int32), _VP]),
+    "dd_op_inner_solve_static": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_int32), _VP]),
     "dd_net_default_params": (None, [ctypes.POINTER(NetParams)]),
     "dd_net_create": (ctypes.c_int, [ctypes.POINTER(NetParams), ctypes.POINTER(_VP)]),
     "dd_net_destroy": (ctypes.c_int, [_VP]),
@@ -389,6 +391,23 @@ class Solver:
                                        iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        _stream(self.torch)), "dd_op_inner_solve")
+        return u, iters, flags
+
+    def op_inner_solve_static(self, f, u=None, counts: bool = True):
+        """dd_op_inner_solve_static: packed f -> (u, iters, flags); with counts=False nothing is
+        copied back and the call does not synchronise (iters, flags are None)."""
+        u = self.torch.empty_like(f) if u is None else u
+        if counts:
+            cnt = self.nsub * self.nrhs
+            iters = np.zeros(cnt, dtype=np.int32)
+            flags = np.zeros(cnt, dtype=np.int32)
+            ip = iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            fp = flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        else:
+            iters = flags = None
+            ip = fp = None
+        _check(lib().dd_op_inner_solve_static(self._h, _ptr(f), _ptr(u), ip, fp, _stream(self.torch)),
+               "dd_op_inner_solve_static")
         return u, iters, flags
 
     # -- two-level method --

@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libddhelm.so")
 ARCH = "gfx950"
 
 SOURCES = ["setup_kernels.hip", "inner_kernels.hip", "direct_kernels.hip", "outer_kernels.hip", "net_kernels.hip",
-           "gcoarse.hip", "multi_kernels.hip", "api.cpp", "net_api.cpp"]
+           "gcoarse.hip", "multi_kernels.hip", "static_scratch.hip", "api.cpp", "net_api.cpp"]
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

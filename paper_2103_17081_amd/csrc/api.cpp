@@ -1181,6 +1181,64 @@ dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void
   return DD_OK;
 }
 
+// Batched subdomain solves with every scratch buffer in the library's static device array
+// (allocates nothing; see include/ddhelm.h).
+extern "C++" template <typename T>
+static dd_status inner_solve_static(dd_handle* h, const void* f, void* u, int32_t* iters, int32_t* flags,
+                                    hipStream_t st) {
+  void* base = nullptr;
+  size_t cap = 0;
+  DD_HIP(ddh::static_scratch(&base, &cap));
+  const size_t ns = (size_t)h->nsub * h->nrhs, nf = (size_t)h->nfine * h->nrhs, mi = (size_t)h->maxit;
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t off = 0;
+  auto take = [&](size_t b) { const size_t o = off; off += up(b); return o; };
+  const size_t o_cnt = take(5 * sizeof(unsigned long long));
+  const size_t o_it = take(ns * sizeof(int));
+  const size_t o_fl = take(ns * sizeof(int));
+  const size_t o_v = take(nf * (mi + 1) * sizeof(cplx<T>));
+  const size_t o_w = take(nf * sizeof(cplx<T>));
+  const size_t o_x = take(nf * sizeof(cplx<T>));
+  const size_t o_r = take(ns * mi * mi * sizeof(cplx<double>));
+  const size_t o_sc = take(ns * (mi + 2) * (size_t)h->max_nc * sizeof(cplx<double>));
+  if (off > cap)
+    return fail(DD_EINVAL, "the subdomain solves of this handle need " + std::to_string(off) +
+                               " bytes of scratch; the static scratch holds " + std::to_string(cap) +
+                               " (lower inner_maxit or the problem size, or use dd_op_inner_solve)");
+  unsigned char* b = (unsigned char*)base;
+  auto a = inner_args<T>(h);
+  a.F = (cplx<T>*)const_cast<void*>(f);   // read only: with no global residual the kernel reads F
+  a.U = (cplx<T>*)u;
+  a.guess = nullptr;
+  a.gtile = nullptr;
+  a.counters = (unsigned long long*)(b + o_cnt);
+  a.iters = (int*)(b + o_it);
+  a.flags = (int*)(b + o_fl);
+  a.V = (cplx<T>*)(b + o_v);
+  a.W = (cplx<T>*)(b + o_w);
+  a.X = (cplx<T>*)(b + o_x);
+  a.R = (cplx<double>*)(b + o_r);
+  a.Sc = (cplx<double>*)(b + o_sc);
+  DD_HIP(ddh::launch_zero_words(a.counters, 5, st));   // the array keeps the previous call's contents
+  DD_HIP(ddh::launch_inner_solve<T>(a, st));
+  if (iters) DD_HIP(hipMemcpyAsync(iters, a.iters, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (flags) DD_HIP(hipMemcpyAsync(flags, a.flags, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (iters || flags) DD_HIP(hipStreamSynchronize(st));
+  return DD_OK;
+}
+
+dd_status dd_op_inner_solve_static(dd_handle* h, const void* f, void* u, int32_t* iters, int32_t* flags,
+                                   void* stream) {
+  DD_TRY(check_handle(h));
+  if (!f || !u || f == u) return fail(DD_EINVAL, "f and u must be distinct non-null device pointers");
+  if (h->direct || h->multi)
+    return fail(DD_EINVAL, "the static-scratch subdomain solves need the fused deflated-GMRES form "
+                           "(local_solver DD_LOCAL_DEFLATED_GMRES, inner_launch DD_INNER_FUSED)");
+  hipStream_t st = (hipStream_t)stream;
+  return h->prec == 32 ? inner_solve_static<float>(h, f, u, iters, flags, st)
+                       : inner_solve_static<double>(h, f, u, iters, flags, st);
+}
+
 // ---- learned initial guess ---------------------------------------------------------------
 
 dd_status dd_set_guess(dd_handle* h, dd_net* net) {

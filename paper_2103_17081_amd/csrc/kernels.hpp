@@ -169,6 +169,13 @@ hipError_t launch_direct_solve(const DirectArgs& a, hipStream_t st);
 size_t direct_lds_bytes(int max_nj);
 hipError_t configure_direct(int max_nj);
 
+// ---- static device scratch (the entry point that allocates nothing) -----------------
+// Device address on the current device, and size, of the library's static scratch array
+// (address looked up once per device with hipGetSymbolAddress).
+hipError_t static_scratch(void** ptr, size_t* bytes);
+// Zero `words` 8-byte words at p with a fill kernel (no memset node under graph capture).
+hipError_t launch_zero_words(void* p, size_t words, hipStream_t st);
+
 // ---- global FP64 operations (outer FGMRES) -----------------------------------------
 hipError_t launch_global_apply(Consts cs, const cplx<double>* v, cplx<double>* w, int nrhs, hipStream_t st);
 
