@@ -18,8 +18,9 @@ def solver_for(name: str, precision: int = 64, local_bc: str = "impedance", **kw
     from paper_2103_17081_amd.binding import Solver
     w = inputs.workload(name)
     kw.setdefault("outer_maxit", {"small": 200, "medium": 2000}.get(name, 4000))
+    kw.setdefault("inner_tol", w.inner_tol)
     return Solver(w.k, n_intervals=w.n, cuts_x=w.cuts_x, cuts_y=w.cuts_y, overlap=w.overlap,
-                  local_bc=local_bc, inner_precision=precision, inner_tol=w.inner_tol, **kw)
+                  local_bc=local_bc, inner_precision=precision, **kw)
 
 
 def check_layout(S, gpu):
