@@ -26,9 +26,14 @@ direct-solve baseline of the paper's experiments) for comparison; `learned_guess
 chosen form with the trained BF16 guess network attached (its output offered to every
 subdomain GMRES, kept only when it lowers the deflated residual); `two_level` times the
 two-level method (a global coarse space added to the chosen form, the extension the
-paper proposes in its conclusions).  `--xlarge-batches` runs only the largest one-GPU
-configuration (k = 400, eight right-hand sides) with the two-level method, as two
-unrestarted batches of four.
+paper proposes in its conclusions).  `tol_sweep` repeats the solve on the medium workload
+(k = 100, N = 160, 8 x 8) at inner tolerances 1e-1, 1e-2 and 1e-4 in the chosen and the
+complex128 forms, with the stored oracle counts beside them; `restart_study` runs the
+one-level chosen form with restarted FGMRES (restart 100, 300, 1000); `xlarge` solves the
+largest one-GPU configuration (k = 400, N = 1274, 32 x 32 perturbed blocks, eight
+right-hand sides) with the two-level method as two unrestarted batches of four, in the
+chosen, complex128 and exact-local-solve forms.  `--xlarge-batches` runs only that leg.
+Progress goes to stderr; stdout carries the one result line.
 """
 
 from __future__ import annotations
@@ -43,6 +48,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def progress(msg: str):
+    """Progress on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 METRIC = "DD-FGMRES time-to-solution (rel res 1e-6) & subdomain solves/s, chosen vs plain"
 
 
@@ -94,6 +104,12 @@ def parse():
                     help="coarse intervals per edge of the two-level leg (0: N / 2, i.e. H = 2h)")
     ap.add_argument("--two-level-only", action="store_true",
                     help="run only the two-level leg and print it (profiling of the coarse correction)")
+    ap.add_argument("--no-tol-sweep", action="store_true",
+                    help="skip the inner-tolerance study on the medium workload (1e-1, 1e-2, 1e-4)")
+    ap.add_argument("--no-restart", action="store_true",
+                    help="skip the restarted-FGMRES study (restart 100, 300, 1000) of the one-level solve")
+    ap.add_argument("--no-xlarge", action="store_true",
+                    help="skip the k = 400 eight-right-hand-side leg (two-level, batches of four)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-outer", type=int, default=40, help="outer iterations of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -102,12 +118,30 @@ def parse():
 
 
 def make_solver(w, precision: int, local_solver: str = "deflated", coarse_intervals: int = 0,
-                inner_launch: str = "fused"):
+                inner_launch: str = "fused", **kw):
     from paper_2103_17081_amd.binding import Solver
+    kw.setdefault("inner_tol", w.inner_tol)
+    kw.setdefault("outer_maxit", 4000)
     return Solver(w.k, n_intervals=w.n, cuts_x=w.cuts_x, cuts_y=w.cuts_y, overlap=w.overlap,
-                  inner_precision=precision, inner_tol=w.inner_tol, outer_tol=w.outer_tol,
-                  outer_maxit=4000, local_solver=local_solver, coarse_intervals=coarse_intervals,
-                  inner_launch=inner_launch, use_graph=inner_launch == "fused")
+                  inner_precision=precision, outer_tol=w.outer_tol, local_solver=local_solver,
+                  coarse_intervals=coarse_intervals, inner_launch=inner_launch,
+                  use_graph=inner_launch == "fused", **kw)
+
+
+def describe(w) -> str:
+    """Workload line: grid, partition (with the width perturbation and its seed), sources."""
+    from paper_2103_17081_amd import inputs
+    px, py = len(w.cuts_x) - 1, len(w.cuts_y) - 1
+    uniform = (list(w.cuts_x) == list(inputs.uniform_cuts(w.n, px))
+               and list(w.cuts_y) == list(inputs.uniform_cuts(w.n, py)))
+    part = (f"{px}x{py} uniform" if uniform else
+            f"{px}x{py} with widths perturbed by +-25% (seed {inputs.SEED_BASE}, x then y)")
+    src = {"small": "unit point source at (0.5, 0.5)",
+           "medium": f"point source + 3 Gaussians (seed {inputs.SEED_BASE} + rhs)",
+           "large": f"3 Gaussians (seed {inputs.SEED_BASE} + rhs)",
+           "xlarge": f"3 Gaussians + a seeded point source per rhs (seed {inputs.SEED_BASE} + rhs)"}[w.name]
+    return (f"{w.name}: k={w.k:g}, N={w.n} ({w.ndof} dofs), {w.nsub} subdomains ({part}, overlap {w.overlap}), "
+            f"{src}, inner tol {w.inner_tol:g}, outer tol {w.outer_tol:g}")
 
 
 def default_coarse_intervals(w) -> int:
@@ -147,7 +181,9 @@ def cpu_baseline(w, outer: int):
             "kind": "oracle",
             "sample": f"first {st.outer_iters} outer FGMRES iterations of workload '{w.name}' "
                       f"({st.subdomain_solves} subdomain solves, avg {st.avg_inner:.1f} inner its) "
-                      f"in {dt:.1f} s; setup excluded; BLAS threads {threads or 'default'}"}
+                      f"in {dt:.1f} s; a per-step rate over those iterations (not a time to solution: the "
+                      f"oracle's full solve of this workload takes hours); setup excluded; "
+                      f"BLAS threads {threads or 'default'}"}
 
 
 GUESS_WEIGHTS = os.path.join(ROOT, "paper_2103_17081_amd", "weights", "guess_t64.ddnet")
@@ -190,9 +226,12 @@ def xlarge_batches(torch, batch: int = 4, maxit: int = 1000):
     from paper_2103_17081_amd.binding import Solver
     w = inputs.workload("xlarge", 8)
     F_all = torch.from_numpy(np.stack(w.rhs)).to("cuda")
-    out = {"workload": f"xlarge: k={w.k:g}, N={w.n} ({w.ndof} dofs), {w.nsub} subdomains, 8 right-hand sides",
+    out = {"workload": describe(w) + ", 8 right-hand sides",
+           "method": "two-level (global coarse space, M = N/2) in every form: the one-level outer count grows "
+                     "with the subdomain count and eight unrestarted one-level bases do not fit in memory",
            "coarse_intervals": default_coarse_intervals(w), "batch": batch, "outer_maxit": maxit}
-    for form, prec, local in (("chosen", 32, "deflated"), ("exact_local_solves", 64, "direct")):
+    for form, prec, local in (("chosen", 32, "deflated"), ("fused_fp64", 64, "deflated"),
+                              ("exact_local_solves", 64, "direct")):
         tot, runs = 0.0, []
         for b0 in range(0, len(w.rhs), batch):
             F = F_all[b0:b0 + batch].contiguous()
@@ -205,16 +244,77 @@ def xlarge_batches(torch, batch: int = 4, maxit: int = 1000):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             R = F - torch.stack([s.op_global_apply(U[q].contiguous()) for q in range(batch)])
-            rel = (torch.linalg.vector_norm(R, dim=1) / torch.linalg.vector_norm(F, dim=1)).max().item()
+            rels = (torch.linalg.vector_norm(R, dim=1) / torch.linalg.vector_norm(F, dim=1)).tolist()
+            rel = max(rels)
             s.close()
             del U, R
             torch.cuda.empty_cache()
             tot += dt
             runs.append({"rhs": [b0, b0 + batch], "time_to_solution_s": dt, "outer_iters": st["outer_iters"],
-                         "true_relres_max": rel, "status": st["status"]})
-            print(json.dumps({form: runs[-1]}), flush=True)
+                         "true_relres_max": rel, "true_relres_per_rhs": rels, "status": st["status"],
+                         "avg_inner_iters": st["inner_iters_total"] / max(st["subdomain_solves"], 1)})
+            progress(f"xlarge {form} rhs {b0}..{b0 + batch - 1}: {dt:.1f} s, {st['outer_iters']} outer")
         out[form] = {"time_to_solution_s": tot, "batches": runs}
     return out
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_counts.json")
+
+
+def tol_sweep_leg(torch, tols=(0.1, 0.01, 1e-4)):
+    """Inner-tolerance study on the medium workload (k = 100, N = 160, 8 x 8): per tolerance,
+    the chosen form (complex64 inner, autotuned, graph replay) and the complex128 inner form
+    (fused kernel), their time to solution, outer count and average inner count, the stored
+    oracle count (tests/golden/oracle_counts.json, written by the oracle), and the
+    FP32-vs-FP64 difference of one preconditioner application on a seeded residual."""
+    import numpy as np
+    from paper_2103_17081_amd import inputs
+    w = inputs.workload("medium")
+    f = torch.from_numpy(w.rhs[0]).to("cuda")
+    rng = np.random.default_rng(72)
+    r = torch.from_numpy(rng.standard_normal(w.ndof) + 1j * rng.standard_normal(w.ndof)).to("cuda")
+    gold = json.load(open(GOLDEN))["medium"] if os.path.exists(GOLDEN) else {}
+    rows = []
+    for tol in tols:
+        row = {"inner_tol": tol}
+        z = {}
+        for form, prec in (("chosen_fp32", 32), ("fused_fp64", 64)):
+            s = make_solver(w, prec, inner_tol=tol, outer_maxit=3000)
+            if prec == 32:
+                s.autotune(None)
+            t, u, st = timed_solves(torch, s, f, 1, 1)
+            z[form] = s.apply_preconditioner(r)
+            row[form] = {"time_to_solution_s": t, "outer_iters": st[-1]["outer_iters"],
+                         "avg_inner_iters": st[-1]["inner_iters_total"] / max(st[-1]["subdomain_solves"], 1),
+                         "true_relres": true_relres(torch, s, f, u), "status": st[-1]["status"]}
+            s.close()
+        row["z_rel_diff_fp32_vs_fp64"] = float(torch.linalg.vector_norm(z["chosen_fp32"] - z["fused_fp64"])
+                                               / torch.linalg.vector_norm(z["fused_fp64"]))
+        g = gold if gold.get("inner_tol") == tol else gold.get("tol_sweep", {}).get(f"{tol:g}")
+        if g:
+            row["oracle_outer_iters"] = g["outer_iters"]
+            row["oracle_avg_inner_iters"] = g["inner_iters"] / g["subdomain_solves"]
+        rows.append(row)
+    return {"workload": describe(w), "rows": rows}
+
+
+def restart_leg(torch, w, f, restarts=(100, 300, 1000), maxit=6000):
+    """The one-level chosen form with restarted FGMRES: outer count, time to solution, and
+    the orthogonalisation share of an instrumented solve (steps launched one by one)."""
+    rows = []
+    for m in restarts:
+        s = make_solver(w, 32, outer_restart=m, outer_maxit=maxit)
+        s.autotune(None)
+        t, u, st = timed_solves(torch, s, f, 1, 0)
+        s.set_graph(False)
+        _, inst = s.solve(f, check=False)
+        torch.cuda.synchronize()
+        rows.append({"restart": m, "time_to_solution_s": t, "outer_iters": st[-1]["outer_iters"],
+                     "status": st[-1]["status"], "true_relres": true_relres(torch, s, f, u),
+                     "orth_share_instrumented": inst["ms_orth"] / max(inst["ms_steps"], 1e-9),
+                     "ms_per_step_instrumented": inst["ms_steps"] / max(inst["precond_applies"], 1)})
+        s.close()
+    return rows
 
 
 def two_level_leg(torch, w, f, M: int, t_one_level=None, direct: bool = True):
@@ -282,6 +382,7 @@ def main():
         M = args.coarse_intervals or default_coarse_intervals(w)
         print(json.dumps({"two_level": two_level_leg(torch, w, f, M, direct=not args.no_direct)}), flush=True)
         return 0
+    progress("chosen form")
     chosen = make_solver(w, 32)
     tune_report = chosen.autotune(None)      # launch configuration measured on this problem (set-up)
     t, u, stats = timed_solves(torch, chosen, f, args.steps, args.warmup)
@@ -323,9 +424,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c64-inner/f64-outer",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: k={w.k:g}, N={w.n} ({w.ndof} dofs), {w.nsub} subdomains "
-                               f"({len(w.cuts_x) - 1}x{len(w.cuts_y) - 1}, overlap {w.overlap}), "
-                               f"inner tol {w.inner_tol:g}, outer tol {w.outer_tol:g}, no restart",
+        "config": {"workload": describe(w) + ", no restart",
                    "form": "chosen (complex64 inner, FP64 coarse LU and outer FGMRES)"},
         "chosen": {"time_to_solution_s": t / args.steps, "outer_iters": last["outer_iters"],
                    "precond_applies": last["precond_applies"],
@@ -345,6 +444,7 @@ def main():
         # plain: complex128 subdomain Krylov work as one batched launch per GMRES stage (all
         # subdomains per launch) with the inner loop on the host, no persistent kernel, outer
         # steps launched one by one (no graph replay)
+        progress("plain form")
         plain = make_solver(w, 64, inner_launch="multi")
         tp, up, sp = timed_solves(torch, plain, f, 1, 1)
         out["plain"] = {"time_to_solution_s": tp, "outer_iters": sp[-1]["outer_iters"],
@@ -368,6 +468,7 @@ def main():
         fused.close()
     if not args.no_direct:
         # the paper's direct-solve baseline: exact FP64 subdomain solves (block factorisation of each B_j)
+        progress("exact local solves")
         direct = make_solver(w, 64, "direct")
         td, ud, sd = timed_solves(torch, direct, f, 1, 1)
         direct.set_graph(False)
@@ -381,11 +482,23 @@ def main():
             "algorithmic_GB_per_apply": di["inner_bytes"] / max(di["precond_applies"], 1) / 1e9}
         direct.close()
     if not args.no_guess:
+        progress("learned guess")
         out["learned_guess"] = guess_leg(torch, w, f, t / args.steps)
     if not args.no_two_level:
+        progress("two-level")
         out["two_level"] = two_level_leg(torch, w, f, args.coarse_intervals or default_coarse_intervals(w),
                                          t / args.steps)
+    if not args.no_tol_sweep:
+        progress("inner-tolerance sweep")
+        out["tol_sweep"] = tol_sweep_leg(torch)
+    if not args.no_restart and args.workload == "large":
+        progress("restart study")
+        out["restart_study"] = restart_leg(torch, w, f)
+    if not args.no_xlarge and args.workload == "large":
+        progress("xlarge")
+        out["xlarge"] = xlarge_batches(torch)
     if not args.no_cpu:
+        progress("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_outer)
     print(json.dumps(out), flush=True)
     return 0

@@ -107,14 +107,23 @@ __device__ __forceinline__ int tw_step_block(int h, int s, int p, int my) {
   return p + 1 + b <= my - 1 ? tw_J(my, p + 1 + b) : -1;
 }
 
-// t_{i+1} -= L_{i+1} a_i (top) for unknown c.
+// `v` if `keep`, else 0 (a select, not a branch).
+__device__ __forceinline__ cplx<double> keep_c(bool keep, cplx<double> v) {
+  return cplx<double>{keep ? v.re : 0.0, keep ? v.im : 0.0};
+}
+
+// t_{i+1} -= L_{i+1} a_i (top) for unknown c.  Neighbours outside the row are read at c
+// with a zero coupling, so all operands are loaded without branches (same sum).
 template <typename Lower>
 __device__ __forceinline__ void tw_couple_down(int mx, Lower lower, int i, int c, cplx<double>* t,
                                                const cplx<double>* a) {
   const cplx<double>* ap = a + i * mx + c;
-  cplx<double> v = t[(i + 1) * mx + c] - lower(i + 1, c, 1) * ap[0];
-  if (c > 0) v = v - lower(i + 1, c, 0) * ap[-1];
-  if (c < mx - 1) v = v - lower(i + 1, c, 2) * ap[1];
+  const bool lo = c > 0, hi = c < mx - 1;
+  const cplx<double> l0 = keep_c(lo, lower(i + 1, c, 0)), l2 = keep_c(hi, lower(i + 1, c, 2));
+  const cplx<double> am = ap[lo ? -1 : 0], a0 = ap[0], ap1 = ap[hi ? 1 : 0];
+  cplx<double> v = t[(i + 1) * mx + c] - lower(i + 1, c, 1) * a0;
+  v = v - l0 * am;
+  v = v - l2 * ap1;
   t[(i + 1) * mx + c] = v;
 }
 
@@ -123,9 +132,12 @@ template <typename Lower>
 __device__ __forceinline__ void tw_couple_up(int mx, Lower lower, int i, int c, cplx<double>* t,
                                              const cplx<double>* a) {
   const cplx<double>* bp = a + i * mx + c;
-  cplx<double> v = t[(i - 1) * mx + c] - lower(i, c, 1) * bp[0];
-  if (c > 0) v = v - lower(i, c - 1, 2) * bp[-1];
-  if (c < mx - 1) v = v - lower(i, c + 1, 0) * bp[1];
+  const bool lo = c > 0, hi = c < mx - 1;
+  const cplx<double> u0 = keep_c(lo, lower(i, lo ? c - 1 : c, 2)), u2 = keep_c(hi, lower(i, hi ? c + 1 : c, 0));
+  const cplx<double> bm = bp[lo ? -1 : 0], b0 = bp[0], bp1 = bp[hi ? 1 : 0];
+  cplx<double> v = t[(i - 1) * mx + c] - lower(i, c, 1) * b0;
+  v = v - u0 * bm;
+  v = v - u2 * bp1;
   t[(i - 1) * mx + c] = v;
 }
 
@@ -207,11 +219,13 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
         if (h == 0 && active && l == 0) a[p * mx + r] = acc;
         lds_barrier();
       } else {
-        // y_i = a_i - H_i y_{i+1} (top), y_i = b_i - J_i y_{i-1} (bottom)
+        // y_i = a_i - H_i y_{i+1} (top), y_i = b_i - J_i y_{i-1} (bottom); a_i is read
+        // before the product so that its load overlaps it
         const int b = s - nf - 1;
         const int i = h == 0 ? p - 1 - b : p + 1 + b;
         const bool on = h == 0 ? i >= 0 : i <= my - 1;
         const int src = h == 0 ? i + 1 : i - 1;
+        const cplx<double> ai = a[(on ? i : p) * mx + (active ? r : 0)];
         cplx<double> acc = czero<double>();
         if (on) {
 #pragma unroll
@@ -219,7 +233,7 @@ __device__ __forceinline__ void twisted_solve_ring(int mx, int my, const cplx<do
         }
         acc.re = row_sum<L>(acc.re);
         acc.im = row_sum<L>(acc.im);
-        if (on && active && l == 0) a[i * mx + r] = a[i * mx + r] - acc;
+        if (on && active && l == 0) a[i * mx + r] = ai - acc;
         lds_barrier();
       }
     }

@@ -88,24 +88,36 @@ __device__ Lds<T> carve(unsigned char* base, int max_nj, int max_nc, int maxit) 
   return L;
 }
 
-// out (=|-=) B_j in over the tile; no synchronisation.
+// `v` if `keep`, else 0 (a select, not a branch).
+template <typename T>
+__device__ __forceinline__ cplx<T> keep_or_zero(bool keep, cplx<T> v) {
+  return cplx<T>{keep ? v.re : T(0), keep ? v.im : T(0)};
+}
+
+// out (=|-=) B_j in over the tile; no synchronisation.  Neighbours outside the tile are
+// read at the node itself and multiplied by zero, so the seven reads of a node are issued
+// together without branches (adding 0 * c leaves the sum unchanged).
 template <typename T, bool kSubtract>
 __device__ __forceinline__ void apply_B(const SubDesc& d, const cplx<T>* tab, const cplx<T>* in, cplx<T>* out) {
   const int nx = d.nx, ny = d.ny, nj = nx * ny;
   for (int n = threadIdx.x; n < nj; n += blockDim.x) {
     const int lj = n / nx, li = n - lj * nx;
     const cplx<T>* c = tab + kStencilPts * node_class(d.i0 + li, d.j0 + lj, d.ax, d.bx, d.ay, d.by);
-    cplx<T> acc = c[kC] * in[n];
-    if (li > 0) acc = cfma(c[kW], in[n - 1], acc);
-    if (li < nx - 1) acc = cfma(c[kE], in[n + 1], acc);
-    if (lj > 0) {
-      acc = cfma(c[kS], in[n - nx], acc);
-      if (li > 0) acc = cfma(c[kSW], in[n - nx - 1], acc);
-    }
-    if (lj < ny - 1) {
-      acc = cfma(c[kN], in[n + nx], acc);
-      if (li < nx - 1) acc = cfma(c[kNE], in[n + nx + 1], acc);
-    }
+    const bool hw = li > 0, he = li < nx - 1, hs = lj > 0, hn = lj < ny - 1;
+    const cplx<T> xc = in[n];
+    const cplx<T> xw = keep_or_zero(hw, in[hw ? n - 1 : n]);
+    const cplx<T> xe = keep_or_zero(he, in[he ? n + 1 : n]);
+    const cplx<T> xs = keep_or_zero(hs, in[hs ? n - nx : n]);
+    const cplx<T> xsw = keep_or_zero(hs && hw, in[hs && hw ? n - nx - 1 : n]);
+    const cplx<T> xn = keep_or_zero(hn, in[hn ? n + nx : n]);
+    const cplx<T> xne = keep_or_zero(hn && he, in[hn && he ? n + nx + 1 : n]);
+    cplx<T> acc = c[kC] * xc;
+    acc = cfma(c[kW], xw, acc);
+    acc = cfma(c[kE], xe, acc);
+    acc = cfma(c[kS], xs, acc);
+    acc = cfma(c[kSW], xsw, acc);
+    acc = cfma(c[kN], xn, acc);
+    acc = cfma(c[kNE], xne, acc);
     out[n] = kSubtract ? out[n] - acc : acc;
   }
 }
@@ -132,15 +144,25 @@ __device__ __forceinline__ void restrict_to(const SubDesc& d, const cplx<T>* v, 
     }
     return;
   }
+  // fine rows/columns 2c, 2c+1, 2c+2 with weights 1/2, 1, 1/2; only 2c+2 can fall outside
+  // the tile, and is then read at 2c+1 with weight 0
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
     const int cy = c / d.mx, cx = c - cy * d.mx;
+    const bool xin = 2 * cx + 2 < d.nx, yin = 2 * cy + 2 < d.ny;
+    const int px[3] = {2 * cx, 2 * cx + 1, xin ? 2 * cx + 2 : 2 * cx + 1};
+    const int py[3] = {2 * cy, 2 * cy + 1, yin ? 2 * cy + 2 : 2 * cy + 1};
+    const double wx[3] = {0.5, 1.0, xin ? 0.5 : 0.0};
+    const double wy[3] = {0.5, 1.0, yin ? 0.5 : 0.0};
+    cplx<T> vv[3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) vv[b][e] = v[py[b] * d.nx + px[e]];
     cplx<double> acc = czero<double>();
-    for (int py = 2 * cy; py <= 2 * cy + 2 && py < d.ny; ++py) {
-      const double wy = zweight(py, cy);
-      for (int px = 2 * cx; px <= 2 * cx + 2 && px < d.nx; ++px) {
-        acc = acc + (wy * zweight(px, cx)) * ccast<double>(v[py * d.nx + px]);
-      }
-    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) acc = acc + (wy[b] * wx[e]) * ccast<double>(vv[b][e]);
     t[c] = acc;
   }
 }
@@ -163,18 +185,30 @@ __device__ __forceinline__ cplx<double> prolong_at(const SubDesc& d, const cplx<
     }
     return acc;
   }
+  // coarse nodes (li - 1) >> 1 and the next one per direction; one outside the coarse grid
+  // is read at a valid node with weight 0
   const int ca = (li - 1) >> 1, cb = (lj - 1) >> 1;
+  double wy[2], wx[2];
+  int by[2], bx[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int b = cb + q, a2 = ca + q;
+    const bool yok = b >= 0 && b < d.my, xok = a2 >= 0 && a2 < d.mx;
+    by[q] = yok ? b : 0;
+    bx[q] = xok ? a2 : 0;
+    wy[q] = yok ? zweight(lj, b) : 0.0;
+    wx[q] = xok ? zweight(li, a2) : 0.0;
+  }
+  cplx<double> yv[2][2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) yv[q][e] = y[by[q] * d.mx + bx[e]];
   cplx<double> acc = czero<double>();
 #pragma unroll
-  for (int b = cb; b <= cb + 1; ++b) {
-    if (b < 0 || b >= d.my) continue;
-    const double wy = zweight(lj, b);
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int a2 = ca; a2 <= ca + 1; ++a2) {
-      if (a2 < 0 || a2 >= d.mx) continue;
-      acc = acc + (wy * zweight(li, a2)) * y[b * d.mx + a2];
-    }
-  }
+    for (int e = 0; e < 2; ++e) acc = acc + (wy[q] * wx[e]) * yv[q][e];
   return acc;
 }
 
@@ -240,9 +274,13 @@ __device__ __forceinline__ double tile_norm(const SubDesc& d, const cplx<T>* v, 
 
 // Gram-Schmidt coefficients against V[0..k]: red[w * S + i] = wave w's partial of
 // conj(V_i) . B for i <= k, and red[w * S + k + 1] = wave w's partial of |B|^2 when
-// with_norm.  Basis vectors are swept kDotChunk at a time so that each thread keeps
-// kDotChunk independent loads per node in flight.
+// with_norm.  The basis is swept kDotChunk vectors at a time and each thread loads the
+// chunk's entries of kSweepNodes nodes at once (indices clamped to valid vectors and nodes,
+// surplus products multiplied by zero), so that many loads are in flight per wave: the
+// sweeps are bound by how many bytes a CU has in flight, not by arithmetic.  Each
+// thread's partial sums still add its nodes in increasing order.
 constexpr int kDotChunk = 8;
+constexpr int kSweepNodes = 1;   // 2 and 4 measured slower over the whole kernel (register pressure)
 template <typename T, int NT>
 __device__ __forceinline__ void basis_dots(const cplx<T>* __restrict__ V, int nj, int k, const cplx<T>* B,
                                            cplx<T>* red, int S, bool with_norm) {
@@ -251,11 +289,25 @@ __device__ __forceinline__ void basis_dots(const cplx<T>* __restrict__ V, int nj
     cplx<T> acc[kDotChunk];
 #pragma unroll
     for (int q = 0; q < kDotChunk; ++q) acc[q] = czero<T>();
-    for (int n = tid; n < nj; n += NT) {
-      const cplx<T> w = B[n];
+    for (int n0 = tid; n0 < nj; n0 += kSweepNodes * NT) {
+      int nn[kSweepNodes];
+      cplx<T> w[kSweepNodes];
 #pragma unroll
-      for (int q = 0; q < kDotChunk; ++q)
-        if (i0 + q <= k) acc[q] = acc[q] + cmulc(V[(long long)(i0 + q) * nj + n], w);
+      for (int e = 0; e < kSweepNodes; ++e) {
+        const int n = n0 + e * NT;
+        nn[e] = n < nj ? n : n0;
+        w[e] = keep_or_zero(n < nj, B[nn[e]]);
+      }
+      cplx<T> v[kSweepNodes][kDotChunk];
+#pragma unroll
+      for (int e = 0; e < kSweepNodes; ++e)
+#pragma unroll
+        for (int q = 0; q < kDotChunk; ++q) v[e][q] = V[(long long)min(i0 + q, k) * nj + nn[e]];
+#pragma unroll
+      for (int e = 0; e < kSweepNodes; ++e)
+#pragma unroll
+        for (int q = 0; q < kDotChunk; ++q)
+          if (i0 + q <= k) acc[q] = acc[q] + cmulc(v[e][q], w[e]);
     }
 #pragma unroll
     for (int q = 0; q < kDotChunk; ++q) {
@@ -275,26 +327,38 @@ __device__ __forceinline__ void basis_dots(const cplx<T>* __restrict__ V, int nj
   }
 }
 
-// B[n] += sgn * sum_{i < cnt} V_i[n] c_i over the tile: the basis is read kUpdChunk vectors
-// at a time with every load of a chunk issued before the first product (indices past cnt
-// are clamped to a valid vector and their coefficient skipped), so a thread waits once per
-// chunk instead of once per basis vector.
+// B[n] (+|-)= sum_{i < cnt} V_i[n] c_i over the tile, chunked like basis_dots: every load
+// of a chunk and of the thread's kSweepNodes nodes is issued before the first product
+// (indices past cnt are clamped to a valid vector and their coefficient skipped).
 constexpr int kUpdChunk = 8;
 template <typename T, int NT, bool kSubtract>
 __device__ __forceinline__ void basis_combine(const cplx<T>* __restrict__ V, int nj, int cnt, const cplx<T>* c,
                                               cplx<T>* B) {
   if (cnt <= 0) return;
-  for (int n = threadIdx.x; n < nj; n += NT) {
-    cplx<T> acc = B[n];
-    for (int i0 = 0; i0 < cnt; i0 += kUpdChunk) {
-      cplx<T> v[kUpdChunk];
+  for (int n0 = threadIdx.x; n0 < nj; n0 += kSweepNodes * NT) {
+    int nn[kSweepNodes];
+    cplx<T> acc[kSweepNodes];
 #pragma unroll
-      for (int q = 0; q < kUpdChunk; ++q) v[q] = V[(long long)min(i0 + q, cnt - 1) * nj + n];
-#pragma unroll
-      for (int q = 0; q < kUpdChunk; ++q)
-        if (i0 + q < cnt) acc = kSubtract ? acc - v[q] * c[i0 + q] : acc + v[q] * c[i0 + q];
+    for (int e = 0; e < kSweepNodes; ++e) {
+      const int n = n0 + e * NT;
+      nn[e] = n < nj ? n : n0;
+      acc[e] = B[nn[e]];
     }
-    B[n] = acc;
+    for (int i0 = 0; i0 < cnt; i0 += kUpdChunk) {
+      cplx<T> v[kSweepNodes][kUpdChunk];
+#pragma unroll
+      for (int e = 0; e < kSweepNodes; ++e)
+#pragma unroll
+        for (int q = 0; q < kUpdChunk; ++q) v[e][q] = V[(long long)min(i0 + q, cnt - 1) * nj + nn[e]];
+#pragma unroll
+      for (int e = 0; e < kSweepNodes; ++e)
+#pragma unroll
+        for (int q = 0; q < kUpdChunk; ++q)
+          if (i0 + q < cnt) acc[e] = kSubtract ? acc[e] - v[e][q] * c[i0 + q] : acc[e] + v[e][q] * c[i0 + q];
+    }
+#pragma unroll
+    for (int e = 0; e < kSweepNodes; ++e)
+      if (n0 + e * NT < nj) B[n0 + e * NT] = acc[e];
   }
 }
 

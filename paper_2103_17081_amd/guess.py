@@ -73,7 +73,7 @@ def make_solver(w, precision: int, **kw) -> Solver:
                   inner_precision=precision, **kw)
 
 
-def collect(w, tile: int, vectors: int = 16, target_tol: float = 1e-8, target_maxit: int = 200):
+def collect(w, tile: int, vectors: int = 16, target_tol: float = 1e-8, target_maxit: int = 60):
     """Training pairs of one problem: (x [n, T, T, 4], t [n, T, T, 2], descs list, info)."""
     import torch
     f = torch.from_numpy(w.rhs[0]).to("cuda")
@@ -99,16 +99,17 @@ def collect(w, tile: int, vectors: int = 16, target_tol: float = 1e-8, target_ma
     return torch.cat(xs), torch.cat(ts), keep, info
 
 
-# Training problems keep every subdomain tile below the network tile and within the
-# LDS budget of the complex128 target solves.
-BLOCK = {32: 20, 64: 32}
+# Training problems: blocks of about 40 cells (widths perturbed by +-25%), the size of the
+# large evaluation workload's subdomains, for the 64 tile; every tile stays below the network
+# tile, and the complex128 target solves (inner_maxit 60) within the kernel's LDS budget.
+BLOCK = {32: 20, 64: 40}
 
 
-def build_dataset(seeds, tile: int, vectors: int = 16, log=print):
+def build_dataset(seeds, tile: int, vectors: int = 16, log=print, block: int | None = None):
     import torch
     X, T, D, infos = [], [], [], []
     for sd in seeds:
-        w = inputs.training_problem(sd, block=BLOCK.get(tile, 32))
+        w = inputs.training_problem(sd, block=block or BLOCK.get(tile, 32))
         t0 = time.perf_counter()
         x, t, d, info = collect(w, tile, vectors)
         info["seconds"] = round(time.perf_counter() - t0, 2)
@@ -254,6 +255,9 @@ def main(argv=None):
     tr.add_argument("--w-res", type=float, default=0.1)
     tr.add_argument("--w-err", type=float, default=1.0)
     tr.add_argument("--eval", default="large", help="workload of the ablation after training ('' for none)")
+    tr.add_argument("--heldout-problems", type=int, default=1)
+    tr.add_argument("--block", type=int, default=0, help="cells per training block (0: by tile)")
+    tr.add_argument("--widths", type=int, nargs=4, default=[16, 32, 64, 64])
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
     if a.cmd in ("ablation", "applies"):
@@ -264,17 +268,19 @@ def main(argv=None):
         log(json.dumps(res))
         net.close()
         return 0
-    X, T, D, infos = build_dataset(range(1000, 1000 + a.problems), a.tile, a.vectors, log)
-    Xv, Tv, Dv, _ = build_dataset([2000], a.tile, a.vectors, log)
-    net = GuessNet(tile=a.tile, max_batch=max(a.batch, 256), train=True)
+    X, T, D, infos = build_dataset(range(1000, 1000 + a.problems), a.tile, a.vectors, log, a.block)
+    Xv, Tv, Dv, _ = build_dataset(range(2000, 2000 + a.heldout_problems), a.tile, a.vectors, log, a.block)
+    net = GuessNet(tuple(a.widths), tile=a.tile, max_batch=max(a.batch, 256), train=True)
     log(f"training pairs {X.shape[0]}, held-out {Xv.shape[0]}, parameters {net.nparams}")
     t0 = time.perf_counter()
     hist = train(net, X, T, D, a.steps, a.batch, a.lr, a.w_res, a.w_err, log=log)
     secs = time.perf_counter() - t0
     vl = validation_loss(net, Xv, Tv, Dv, a.w_res, a.w_err)
-    log(f"trained {a.steps} steps in {secs:.1f} s; held-out loss {vl:.4f}")
+    tl = validation_loss(net, X[:Xv.shape[0]], T[:Xv.shape[0]], D[:Xv.shape[0]], a.w_res, a.w_err)
+    log(f"trained {a.steps} steps in {secs:.1f} s; training-set loss {tl:.4f}, held-out loss {vl:.4f}")
     meta = dict(problems=infos, steps=a.steps, batch=a.batch, lr=a.lr, w_res=a.w_res, w_err=a.w_err,
-                final_loss=hist[-1][1], heldout_loss=vl, train_seconds=round(secs, 1))
+                final_loss=hist[-1][1], heldout_loss=vl, train_loss=tl, train_pairs=int(X.shape[0]),
+                heldout_pairs=int(Xv.shape[0]), train_seconds=round(secs, 1))
     save_weights(net, a.out, meta)
     log(f"wrote {a.out}")
     if a.eval:

@@ -2,6 +2,7 @@
 
 Usage: python tests/golden/make_golden.py small [medium] [large]
        python tests/golden/make_golden.py --tol-sweep medium 0.1 0.0001
+       python tests/golden/make_golden.py --spread-tol medium 0.1 16
        python tests/golden/make_golden.py --spread small [medium]
        python tests/golden/make_golden.py --direct small [medium] [large]
        python tests/golden/make_golden.py --two-level small:16 [medium:80]
@@ -307,6 +308,22 @@ if __name__ == "__main__":
             sp = spread(name, 8 if name == "small" else 2)
             store(OUT, lambda d: d.setdefault(name, {}).update({"fp32_perturbed_outer": sp}))
             print(name, sp, flush=True)
+    elif args and args[0] == "--spread-tol":
+        # --spread-tol NAME TOL SEEDS: the FP32-perturbation spread of the outer count at one
+        # inner tolerance, stored beside that tolerance's golden (the workload's own tolerance
+        # at the entry's top level, others under tol_sweep)
+        name, tol, seeds = args[1], float(args[2]), int(args[3])
+        sp = spread(name, seeds, tol)
+        key = f"{tol:g}"
+
+        def put(d):
+            e = d.setdefault(name, {})
+            if e.get("inner_tol") == tol:
+                e["fp32_perturbed_outer"] = sp
+            else:
+                e.setdefault("tol_sweep", {}).setdefault(key, {})["fp32_perturbed_outer"] = sp
+        store(OUT, put)
+        print(name, key, sp, flush=True)
     elif args and args[0] == "--tol-sweep":
         tol_sweep(args[1], [float(t) for t in args[2:]])
     else:
