@@ -358,11 +358,12 @@ __device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double
     detail::coarse_solve_paired<NT>(d, F, t, a);
     return;
   }
-  // the two halves run the two sweeps: 512 threads give 8 lanes per block row (mx <= 32)
-  // and a ring of 8 steps, 256 threads 4 lanes and a ring of 4 (register budget)
+  // the two halves run the two sweeps: 512 threads give 8 lanes per block row (mx <= 32),
+  // 256 threads 4 lanes; rings of 4 steps (with 8 at 512 threads the subdomain-solve kernel
+  // holds 16 more registers per lane and its stencil and coarse-solve steps run 3% slower)
   auto lower = [lc, mx = d.mx](int i, int c, int e) { return lc[3 * (i * mx + c) + e]; };
   if (d.mx <= 32) {
-    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 8, NT / 2>(d.mx, d.my, F, lower, t, a);
+    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 4, NT / 2>(d.mx, d.my, F, lower, t, a);
     else detail::twisted_solve_ring<4, 8, 4, NT / 2>(d.mx, d.my, F, lower, t, a);
   } else {
     detail::twisted_solve_plain<NT / 2>(d.mx, d.my, F, lower, t, a);

@@ -26,7 +26,7 @@ import time
 import numpy as np
 
 from . import inputs
-from .binding import GuessNet, Solver, TileDesc
+from .binding import DDError, GuessNet, Solver, TileDesc
 
 MAGIC = b"DDHNET01"
 
@@ -83,7 +83,15 @@ def collect(w, tile: int, vectors: int = 16, target_tol: float = 1e-8, target_ma
         js = sorted(set(np.linspace(0, max(m - 1, 0), vectors).round().astype(int).tolist()))
         basis = [s32.outer_basis(j).clone() for j in js]
     xs, ts, keep = [], [], []
-    with make_solver(w, 64, inner_tol=target_tol, inner_maxit=target_maxit, use_graph=False) as s64:
+    try:
+        s64 = make_solver(w, 64, inner_tol=target_tol, inner_maxit=target_maxit, use_graph=False)
+    except DDError as e:
+        # the largest tiles of a problem may not fit the complex128 kernel's LDS at this
+        # iteration cap: fewer kept iterations (targets that do not converge are dropped)
+        if "LDS" not in str(e):
+            raise
+        s64 = make_solver(w, 64, inner_tol=target_tol, inner_maxit=target_maxit * 2 // 3, use_graph=False)
+    with s64:
         descs = list(s64.tile_descs())
         for v in basis:
             x, s = s64.tiles(v, tile)
