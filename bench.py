@@ -29,7 +29,7 @@ two-level method (a global coarse space added to the chosen form, the extension 
 paper proposes in its conclusions).  `tol_sweep` repeats the solve on the medium workload
 (k = 100, N = 160, 8 x 8) at inner tolerances 1e-1, 1e-2 and 1e-4 in the chosen and the
 complex128 forms, with the stored oracle counts beside them; `restart_study` runs the
-one-level chosen form with restarted FGMRES (restart 100, 300, 1000); `xlarge` solves the
+one-level chosen form with restarted FGMRES (restart 100, 300, 1000, 2000); `xlarge` solves the
 largest one-GPU configuration (k = 400, N = 1274, 32 x 32 perturbed blocks, eight
 right-hand sides) with the two-level method as two unrestarted batches of four, in the
 chosen, complex128 and exact-local-solve forms.  `--xlarge-batches` runs only that leg.
@@ -107,7 +107,7 @@ def parse():
     ap.add_argument("--no-tol-sweep", action="store_true",
                     help="skip the inner-tolerance study on the medium workload (1e-1, 1e-2, 1e-4)")
     ap.add_argument("--no-restart", action="store_true",
-                    help="skip the restarted-FGMRES study (restart 100, 300, 1000) of the one-level solve")
+                    help="skip the restarted-FGMRES study (restart 100, 300, 1000, 2000) of the one-level solve")
     ap.add_argument("--no-xlarge", action="store_true",
                     help="skip the k = 400 eight-right-hand-side leg (two-level, batches of four)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -298,7 +298,7 @@ def tol_sweep_leg(torch, tols=(0.1, 0.01, 1e-4)):
     return {"workload": describe(w), "rows": rows}
 
 
-def restart_leg(torch, w, f, restarts=(100, 300, 1000), maxit=6000):
+def restart_leg(torch, w, f, restarts=(100, 300, 1000, 2000), maxit=6000):
     """The one-level chosen form with restarted FGMRES: outer count, time to solution, and
     the orthogonalisation share of an instrumented solve (steps launched one by one)."""
     rows = []
