@@ -127,9 +127,10 @@ typedef struct {
   /* Algorithmic bytes of the subdomain-solve kernel summed over its launches: per solve,
      gather 16 n_j + scatter 16 owned_j (32 when the two-level correction is added) +
      (k_j + 1) coarse-factor reads of 16 ((2 my - 1) mx^2 + 3 mx my) bytes + the coarse vectors kept for the
-     recovery 16 nc (2 k_j + 2) + Krylov traffic s n_j (2 k_j + 2 k_j (k_j + 1))
-     (basis writes, CGS2 reads, final combination) + local rhs write/read 2 s n_j, with
-     s = 8 (FP32) or 16 bytes per complex value. */
+     recovery 16 nc (2 k_j + 2) + Krylov traffic s n_j (1 + 3 k_j + 3 k_j (k_j + 1) / 2) when
+     k_j > 0 (basis writes 1 + 2 k_j, three delayed-CGS2 sweeps per iteration reading
+     3 k_j (k_j + 1) / 2 basis vectors in all, final combination k_j) + local rhs write/read
+     2 s n_j, with s = 8 (FP32) or 16 bytes per complex value. */
   double inner_bytes;
   /* The two basis sweeps of the outer delayed CGS2 (events around each launch):
      dot sweep reads the j basis vectors and two vectors, 16 nd (j + 2) bytes at step j;

@@ -562,7 +562,7 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     }
     if (h->prec == 32) DD_TRY(alloc_inner<float>(h));
     else DD_TRY(alloc_inner<double>(h));
-    DD_TRY(h->alloc(&h->R, (size_t)h->nsub * h->nrhs * h->maxit * h->maxit));
+    DD_TRY(h->alloc(&h->R, (size_t)h->nsub * h->nrhs * 2 * h->maxit * h->maxit));
     DD_TRY(h->alloc(&h->Sc, (size_t)h->nsub * h->nrhs * (h->maxit + 2) * h->max_nc));
     DD_TRY(h->alloc(&h->iters, (size_t)h->nsub * h->nrhs));
     DD_TRY(h->alloc(&h->flags, (size_t)h->nsub * h->nrhs));
@@ -1199,7 +1199,7 @@ static dd_status inner_solve_static(dd_handle* h, const void* f, void* u, int32_
   const size_t o_v = take(nf * (mi + 1) * sizeof(cplx<T>));
   const size_t o_w = take(nf * sizeof(cplx<T>));
   const size_t o_x = take(nf * sizeof(cplx<T>));
-  const size_t o_r = take(ns * mi * mi * sizeof(cplx<double>));
+  const size_t o_r = take(ns * 2 * mi * mi * sizeof(cplx<double>));
   const size_t o_sc = take(ns * (mi + 2) * (size_t)h->max_nc * sizeof(cplx<double>));
   if (off > cap)
     return fail(DD_EINVAL, "the subdomain solves of this handle need " + std::to_string(off) +

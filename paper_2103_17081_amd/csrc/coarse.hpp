@@ -359,12 +359,13 @@ __device__ __forceinline__ void coarse_solve(const SubDesc& d, const cplx<double
     return;
   }
   // the two halves run the two sweeps: 512 threads give 8 lanes per block row (mx <= 32),
-  // 256 threads 4 lanes; rings of 4 steps (with 8 at 512 threads the subdomain-solve kernel
-  // holds 16 more registers per lane and its stencil and coarse-solve steps run 3% slower)
+  // 256 threads 4 lanes; rings of 3 steps (a deeper ring makes the subdomain-solve kernel
+  // spill the ring's column offsets to scratch inside the step loop, where each reload
+  // waits for every factor load in flight)
   auto lower = [lc, mx = d.mx](int i, int c, int e) { return lc[3 * (i * mx + c) + e]; };
   if (d.mx <= 32) {
-    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 4, NT / 2>(d.mx, d.my, F, lower, t, a);
-    else detail::twisted_solve_ring<4, 8, 4, NT / 2>(d.mx, d.my, F, lower, t, a);
+    if constexpr (NT >= 512) detail::twisted_solve_ring<8, 4, 3, NT / 2>(d.mx, d.my, F, lower, t, a);
+    else detail::twisted_solve_ring<4, 8, 3, NT / 2>(d.mx, d.my, F, lower, t, a);
   } else {
     detail::twisted_solve_plain<NT / 2>(d.mx, d.my, F, lower, t, a);
   }

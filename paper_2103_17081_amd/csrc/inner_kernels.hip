@@ -2,7 +2,7 @@
 // (Sec. 2, eq. 4; Sec. 3), all subdomains and right-hand sides in one launch.
 //
 // One workgroup carries one (subdomain, right-hand side) pair through its whole
-// solve -- gather, deflated-operator applications, CGS2 Arnoldi with Givens
+// solve -- gather, deflated-operator applications, delayed-CGS2 Arnoldi with Givens
 // rotations, its own convergence test, solution recovery, scatter -- so solves of
 // uneven size and uneven iteration count run side by side without host round trips.
 // Fine-level vectors are in the template precision T; the coarse solve is FP64.
@@ -10,11 +10,15 @@
 // Per solve, with f = R_j r:
 //   P f = f - B Z E^{-1} Z^T f,   reference norm ||P f||;
 //   optional guess g accepted iff ||P f - P B g|| < ||P f||, else x0 = 0;
-//   Arnoldi on w = P B v (deflated operator), classical Gram-Schmidt applied twice;
+//   Arnoldi on the deflated operator P B with classical Gram-Schmidt applied twice in
+//   the delayed form of Swirydowicz, Langou, Ananthan, Yang and Thomas (2020): the
+//   operator is applied to the candidate u~_j before its second orthogonalisation, and
+//   u~_j = V_j s + alpha_j v_j, so P B U~_k = V_{k+1} H_k with U~_k = V_k T_k (T upper
+//   triangular, column j = (s, alpha_j));
 //   stop when the least-squares residual estimate <= tol * ||P f||;
-//   x = x0 + V y,  u = x + Z E^{-1} Z^T (f - B x)   (so f - B u = P (f - B x));
+//   x = x0 + U~ y = x0 + V (T y),  u = x + Z E^{-1} Z^T (f - B x)   (so f - B u = P (f - B x));
 //   the coarse vector of the recovery is assembled from those the solve already formed,
-//   E^{-1} Z^T (f - B x) = E^{-1} Z^T f - E^{-1} Z^T B x0 - sum_i y_i E^{-1} Z^T B v_i,
+//   E^{-1} Z^T (f - B x) = E^{-1} Z^T f - E^{-1} Z^T B x0 - sum_i y_i E^{-1} Z^T B u~_i,
 //   so it costs no deflated application of its own;
 //   z(owned nodes of j) = u.
 #include <algorithm>
@@ -34,8 +38,11 @@ struct Lds {
   cplx<T>* A;          // fine tile (stencil input)
   cplx<T>* B;          // fine tile (stencil output / working vector)
   cplx<T>* tab;        // 9 row classes x 7 coefficients
-  cplx<T>* red;        // wave partial sums, kWavesPerBlock x stride
-  cplx<T>* hT;         // Gram-Schmidt coefficients of the current pass
+  cplx<T>* red;        // wave partial sums, (threads / wave) x stride
+  cplx<T>* hT;         // update coefficients of the new basis vector (s / alpha); then T y
+  cplx<T>* hU;         // update coefficients of the next candidate
+  cplx<double>* sv;    // V_j^H u~_j, then |u~_j|^2
+  cplx<double>* cv;    // V_j^H w, u~_j^H w, |w|^2
   cplx<double>* ct;    // coarse right-hand side
   cplx<double>* ca;    // coarse solution
   cplx<double>* lc;    // lower couplings of E staged for the coarse solve (3 per coarse node)
@@ -55,7 +62,8 @@ __host__ __device__ size_t lds_bytes(int max_nj, int max_nc, int maxit, int nt) 
   b += 2 * align16((size_t)max_nj * sizeof(cplx<T>));
   b += align16(kClasses * kStencilPts * sizeof(cplx<T>));
   b += align16((size_t)(nt / kWave) * s * sizeof(cplx<T>));
-  b += align16(s * sizeof(cplx<T>));
+  b += 2 * align16(s * sizeof(cplx<T>));
+  b += 2 * align16(s * sizeof(cplx<double>));
   b += 2 * align16((size_t)max_nc * sizeof(cplx<double>));
   b += align16((size_t)3 * max_nc * sizeof(cplx<double>));
   b += 3 * align16(s * sizeof(cplx<double>));
@@ -76,6 +84,9 @@ __device__ Lds<T> carve(unsigned char* base, int max_nj, int max_nc, int maxit) 
   L.tab = (cplx<T>*)take(kClasses * kStencilPts * sizeof(cplx<T>));
   L.red = (cplx<T>*)take((size_t)(NT / kWave) * s * sizeof(cplx<T>));
   L.hT = (cplx<T>*)take(s * sizeof(cplx<T>));
+  L.hU = (cplx<T>*)take(s * sizeof(cplx<T>));
+  L.sv = (cplx<double>*)take(s * sizeof(cplx<double>));
+  L.cv = (cplx<double>*)take(s * sizeof(cplx<double>));
   L.ct = (cplx<double>*)take((size_t)max_nc * sizeof(cplx<double>));
   L.ca = (cplx<double>*)take((size_t)max_nc * sizeof(cplx<double>));
   L.lc = (cplx<double>*)take((size_t)3 * max_nc * sizeof(cplx<double>));
@@ -362,10 +373,52 @@ __device__ __forceinline__ void basis_combine(const cplx<T>* __restrict__ V, int
   }
 }
 
+// Delayed-CGS2 update sweep: with u = u~_j in slot j of V and w in LDS, at every node
+//   v_j     = u / alpha - sum_{i<j} V_i ca_i              (written to slot j, over u)
+//   u~_{j+1} = (w - sum_{i<j} V_i cb_i - u e) / gamma      (written to slot j + 1 and the tile)
+// one load of each basis entry for both outputs, chunked like basis_combine.
+template <typename T, int NT>
+__device__ __forceinline__ void basis_update2(cplx<T>* V, int nj, int j, const cplx<T>* ca, const cplx<T>* cb,
+                                              T inv_alpha, cplx<T> e, T inv_gamma, const cplx<T>* w,
+                                              cplx<T>* tile) {
+  cplx<T>* Vj = V + (long long)j * nj;
+  cplx<T>* Vn = Vj + nj;
+  for (int n = threadIdx.x; n < nj; n += NT) {
+    const cplx<T> uo = Vj[n], wn = w[n];
+    cplx<T> aa = czero<T>(), ab = czero<T>();
+    for (int i0 = 0; i0 < j; i0 += kUpdChunk) {
+      cplx<T> v[kUpdChunk];
+#pragma unroll
+      for (int q = 0; q < kUpdChunk; ++q) v[q] = V[(long long)min(i0 + q, j - 1) * nj + n];
+#pragma unroll
+      for (int q = 0; q < kUpdChunk; ++q) {
+        if (i0 + q < j) {
+          aa = cfma(v[q], ca[i0 + q], aa);
+          ab = cfma(v[q], cb[i0 + q], ab);
+        }
+      }
+    }
+    const cplx<T> un = inv_gamma * (wn - ab - uo * e);
+    Vj[n] = inv_alpha * uo - aa;
+    Vn[n] = un;
+    tile[n] = un;
+  }
+}
+
 template <typename T>
 __host__ __device__ constexpr double breakdown_eps() { return sizeof(T) == 4 ? 4e-6 : 1e-14; }
 
 }  // namespace
+
+// A value every lane holds alike (a workgroup sum read back from LDS), moved to scalar
+// registers: the Krylov loop keeps such values live, and in vector registers they would
+// push the coarse solve's factor ring into scratch.
+__device__ __forceinline__ double uniform_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
@@ -384,9 +437,12 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   cplx<T>* W = a.W + fo;
   cplx<T>* X = a.X + fo;
   cplx<T>* V = a.V + fo * (maxit + 1);
-  cplx<double>* R = a.R + (long long)sidx * maxit * maxit;
+  // R factor of the rotated Hessenberg matrix, then T (candidates in the orthonormal basis),
+  // each maxit x maxit with column c at c * maxit
+  cplx<double>* R = a.R + (long long)sidx * 2 * maxit * maxit;
+  cplx<double>* Tm = R + (long long)maxit * maxit;
   // coarse vectors kept for the recovery: slot 0 E^{-1} Z^T f, slot 1 E^{-1} Z^T B x0, slot 2 + i
-  // E^{-1} Z^T B v_i (written and read back by the same thread for each entry)
+  // E^{-1} Z^T B u~_i (written and read back by the same thread for each entry)
   cplx<double>* Sc = a.Sc ? a.Sc + (long long)sidx * (maxit + 2) * a.max_nc : nullptr;
   auto keep_coarse = [&](int slot) {
     if (Sc)
@@ -412,7 +468,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       fn2 += cabs2(ccast<double>(F[n]));
     }
   }
-  const double fnorm = sqrt(block_sum_f64<NT>(fn2, (double*)L.red));
+  const double fnorm = uniform_f64(sqrt(block_sum_f64<NT>(fn2, (double*)L.red)));
   const double fscale = fnorm > 0.0 ? 1.0 / fnorm : 0.0;
   // F holds the scaled right-hand side when gathered here; a caller-supplied F is
   // left untouched and scaled on use (fmul).
@@ -438,7 +494,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   lds_barrier();
   apply_B<T, true>(d, L.tab, L.A, L.B);
   lds_barrier();
-  const double ref = tile_norm<T, NT>(d, L.B, L);
+  const double ref = uniform_f64(tile_norm<T, NT>(d, L.B, L));
 
   bool accepted = false;
   const bool offered = ref > 0.0 && (a.guess || a.gtile);
@@ -470,7 +526,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       for (int n = tid; n < nj; n += NT) L.B[n] = W[n] - L.B[n];
       lds_barrier();
       const double rn = tile_norm<T, NT>(d, L.B, L);
-      accepted = rn < ref;
+      accepted = __builtin_amdgcn_readfirstlane(rn < ref ? 1 : 0) != 0;
       if (!accepted) {
         for (int n = tid; n < nj; n += NT) L.B[n] = W[n];
         lds_barrier();
@@ -479,87 +535,140 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
     const double beta = accepted ? tile_norm<T, NT>(d, L.B, L) : ref;
     converged = beta <= a.tol * ref;
     if (!converged) {
+      // candidate u~_0 = r0 / beta in slot 0 and tile A
       const T inv = T(1.0 / beta);
       for (int n = tid; n < nj; n += NT) {
         const cplx<T> v = inv * L.B[n];
         V[n] = v;
         L.A[n] = v;
       }
-      if (tid == 0) L.g[0] = cplx<double>{beta, 0.0};
+      if (tid == 0) {
+        L.g[0] = cplx<double>{beta, 0.0};
+        L.ctrl[0] = 0;
+      }
       __syncthreads();
     }
     const int S = L.stride;
-    while (!converged && k < maxit) {
-      deflated_op<T, NT>(d, a.fac, L);   // tile B = P B v_k
-      keep_coarse(2 + k);
-      // classical Gram-Schmidt, applied twice
-      for (int pass = 0; pass < 2; ++pass) {
-        basis_dots<T, NT>(V, nj, k, L.B, L.red, S, pass == 0);
-        lds_barrier();
-        for (int i = tid; i <= k + (pass == 0 ? 1 : 0); i += NT) {
-          cplx<double> sacc = czero<double>();
+    // Iteration j: (1) s = V_j^H u~_j, nu = |u~_j|^2, alpha = sqrt(nu - |s|^2); column j-1 of
+    // H becomes final (tentative column + gamma_j s, subdiagonal gamma_j alpha), is rotated,
+    // and the residual estimate decides convergence before the operator is applied;
+    // (2) w = P B u~_j; (3) c = V_j^H w, mu = u~_j^H w, omega = |w|^2; tentative column j:
+    // c and h_jj = (mu - s^H c) / alpha; gamma_{j+1} from Pythagoras (a scale only: the
+    // next step's nu corrects it exactly); (4) one update sweep writes v_j and u~_{j+1}.
+    int j = 0;
+    while (!converged) {
+      basis_dots<T, NT>(V, nj, j - 1, L.A, L.red, S, true);
+      lds_barrier();
+      for (int i = tid; i <= j; i += NT) {
+        cplx<double> sacc = czero<double>();
 #pragma unroll
-          for (int w = 0; w < NT / kWave; ++w) sacc = sacc + ccast<double>(L.red[w * S + i]);
-          if (i <= k) {
-            L.hT[i] = ccast<T>(sacc);
-            L.h[i] = pass == 0 ? sacc : L.h[i] + sacc;
-          } else {
-            L.scal[2] = sqrt(sacc.re);       // ||w|| before orthogonalisation
-          }
-        }
-        lds_barrier();
-        basis_combine<T, NT, true>(V, nj, k + 1, L.hT, L.B);
-        lds_barrier();
-      }
-      const double hnext = tile_norm<T, NT>(d, L.B, L);
-      if (tid == 0) {
-        cplx<double>* col = L.h;
-        for (int i = 0; i < k; ++i) {
-          const cplx<double> x0 = col[i], x1 = col[i + 1];
-          col[i] = L.cs[i] * x0 + L.sn[i] * x1;
-          col[i + 1] = L.cs[i] * x1 - cplx<double>{L.sn[i].re, -L.sn[i].im} * x0;
-        }
-        const cplx<double> av = col[k];
-        const double aa = sqrt(cabs2(av));
-        double c;
-        cplx<double> sv, r;
-        if (hnext == 0.0) {
-          c = 1.0; sv = czero<double>(); r = av;
-        } else if (aa == 0.0) {
-          c = 0.0; sv = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
-        } else {
-          const double t = hypot(aa, hnext);
-          const cplx<double> ph = cplx<double>{av.re / aa, av.im / aa};
-          c = aa / t;
-          sv = (hnext / t) * ph;
-          r = t * ph;
-        }
-        L.cs[k] = c;
-        L.sn[k] = sv;
-        col[k] = r;
-        for (int i = 0; i <= k; ++i) R[(long long)k * maxit + i] = col[i];
-        const cplx<double> gk = L.g[k];
-        L.g[k + 1] = czero<double>() - cplx<double>{sv.re, -sv.im} * gk;
-        L.g[k] = c * gk;
-        const double res = sqrt(cabs2(L.g[k + 1]));
-        const bool brk = hnext <= breakdown_eps<T>() * L.scal[2];
-        L.ctrl[0] = (res <= a.tol * ref || brk) ? 1 : 0;
-        L.scal[1] = hnext;
+        for (int w = 0; w < NT / kWave; ++w) sacc = sacc + ccast<double>(L.red[w * S + i]);
+        L.sv[i] = sacc;
       }
       lds_barrier();
-      converged = L.ctrl[0] != 0;
-      ++k;
-      if (!converged && k < maxit) {
-        const T inv = T(1.0 / L.scal[1]);
-        cplx<T>* Vk = V + (long long)k * nj;
-        for (int n = tid; n < nj; n += NT) {
-          const cplx<T> v = inv * L.B[n];
-          Vk[n] = v;
-          L.A[n] = v;
+      if (tid == 0) {
+        double ss = 0.0;
+        for (int i = 0; i < j; ++i) ss += cabs2(L.sv[i]);
+        const double nu = L.sv[j].re;
+        const double a2 = nu - ss, afloor = 1e-30 * (nu > 0.0 ? nu : 1.0);
+        const double alpha = sqrt(a2 > afloor ? a2 : afloor);
+        L.scal[0] = 1.0 / alpha;
+        L.scal[1] = alpha;
+        if (j == 0) {
+          L.g[0] = alpha * L.g[0];
+        } else {
+          const int c0 = j - 1;
+          cplx<double>* col = L.h;
+          const double gm = L.scal[3];
+          for (int i = 0; i <= c0; ++i) col[i] = col[i] + gm * L.sv[i];
+          for (int i = 0; i < c0; ++i) {
+            const cplx<double> x0 = col[i], x1 = col[i + 1];
+            col[i] = L.cs[i] * x0 + L.sn[i] * x1;
+            col[i + 1] = L.cs[i] * x1 - cplx<double>{L.sn[i].re, -L.sn[i].im} * x0;
+          }
+          const double hnext = gm * alpha;
+          const cplx<double> av = col[c0];
+          const double aa = sqrt(cabs2(av));
+          double c;
+          cplx<double> sv, r;
+          if (hnext == 0.0) {
+            c = 1.0; sv = czero<double>(); r = av;
+          } else if (aa == 0.0) {
+            c = 0.0; sv = cplx<double>{1.0, 0.0}; r = cplx<double>{hnext, 0.0};
+          } else {
+            const double t = hypot(aa, hnext);
+            const cplx<double> ph = cplx<double>{av.re / aa, av.im / aa};
+            c = aa / t;
+            sv = (hnext / t) * ph;
+            r = t * ph;
+          }
+          L.cs[c0] = c;
+          L.sn[c0] = sv;
+          col[c0] = r;
+          for (int i = 0; i <= c0; ++i) R[(long long)c0 * maxit + i] = col[i];
+          const cplx<double> gk = L.g[c0];
+          L.g[c0 + 1] = czero<double>() - cplx<double>{sv.re, -sv.im} * gk;
+          L.g[c0] = c * gk;
+          const double res = sqrt(cabs2(L.g[c0 + 1]));
+          const bool brk = hnext <= breakdown_eps<T>() * L.scal[2];
+          L.ctrl[0] = (res <= a.tol * ref || brk) ? 1 : 0;
         }
-        __syncthreads();
       }
+      lds_barrier();
+      converged = __builtin_amdgcn_readfirstlane(L.ctrl[0]) != 0;
+      if (converged || j == maxit) break;
+      {
+        // column j of T and the update coefficients of v_j
+        const double inv_alpha = L.scal[0];
+        cplx<double>* Tc = Tm + (long long)j * maxit;
+        for (int i = tid; i <= j; i += NT) {
+          Tc[i] = i < j ? L.sv[i] : cplx<double>{L.scal[1], 0.0};
+          if (i < j) L.hT[i] = ccast<T>(inv_alpha * L.sv[i]);
+        }
+      }
+      deflated_op<T, NT>(d, a.fac, L);   // tile B = w = P B u~_j (tile A overwritten)
+      keep_coarse(2 + j);
+      basis_dots<T, NT>(V, nj, j, L.B, L.red, S, true);
+      lds_barrier();
+      for (int i = tid; i <= j + 1; i += NT) {
+        cplx<double> sacc = czero<double>();
+#pragma unroll
+        for (int w = 0; w < NT / kWave; ++w) sacc = sacc + ccast<double>(L.red[w * S + i]);
+        L.cv[i] = sacc;
+      }
+      lds_barrier();
+      if (tid == 0) {
+        cplx<double> sTc = czero<double>();
+        double cc = 0.0;
+        for (int i = 0; i < j; ++i) {
+          sTc = sTc + cmulc(L.sv[i], L.cv[i]);
+          cc += cabs2(L.cv[i]);
+        }
+        const double inv_alpha = L.scal[0];
+        const cplx<double> hjj = inv_alpha * (L.cv[j] - sTc);
+        const double om = L.cv[j + 1].re;
+        double g2 = om - cc - cabs2(hjj);
+        const double gfloor = 1e-28 * (om > 0.0 ? om : 1.0);
+        if (!(g2 > gfloor)) g2 = gfloor;
+        const double gm = sqrt(g2);
+        for (int i = 0; i < j; ++i) L.h[i] = L.cv[i];
+        L.h[j] = hjj;
+        const cplx<double> e = inv_alpha * hjj;
+        L.scal[2] = sqrt(om > 0.0 ? om : 0.0);   // ||w||: breakdown scale of column j
+        L.scal[3] = gm;
+        L.scal[4] = 1.0 / gm;
+        L.scal[6] = e.re;
+        L.scal[7] = e.im;
+      }
+      lds_barrier();
+      const cplx<double> e{L.scal[6], L.scal[7]};
+      for (int i = tid; i < j; i += NT) L.hU[i] = ccast<T>(L.cv[i] - L.sv[i] * e);
+      lds_barrier();
+      basis_update2<T, NT>(V, nj, j, L.hT, L.hU, T(L.scal[0]), ccast<T>(e), T(L.scal[4]), L.B, L.A);
+      __syncthreads();
+      ++j;
     }
+    k = j;
     // y = R^{-1} g (upper triangular, k x k).  R is copied into the free tile A first when
     // it fits (all threads load it side by side), so the serial substitution reads LDS.
     const bool r_lds = (size_t)k * k * sizeof(cplx<double>) <= (size_t)a.max_nj * sizeof(cplx<T>);
@@ -581,7 +690,12 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       }
     }
     lds_barrier();
-    for (int i = tid; i < k; i += NT) L.hT[i] = ccast<T>(L.h[i]);
+    // x coefficients in the orthonormal basis: T y (T upper triangular)
+    for (int i = tid; i < k; i += NT) {
+      cplx<double> acc = czero<double>();
+      for (int l = i; l < k; ++l) acc = acc + Tm[(long long)l * maxit + i] * L.h[l];
+      L.hT[i] = ccast<T>(acc);
+    }
     lds_barrier();
   }
   // x = x0 + V y   (tile A)
@@ -655,7 +769,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
       const unsigned long long ncp = (unsigned long long)d.ncp;
       unsigned long long bytes = 16ull * nn + (a.zadd ? 32ull : 16ull) * own +
                                  (Sc ? (kk + 1) * fac_bytes + 16ull * ncp * (2 * kk + 2) : (kk + 2) * fac_bytes) +
-                                 s * nn * (2 * kk + 2 * kk * (kk + 1)) + 2 * s * nn;
+                                 (kk ? s * nn * (1 + 3 * kk + 3 * kk * (kk + 1) / 2) : 0ull) + 2 * s * nn;
       if (offered) bytes += fac_bytes + (a.gtile ? 8ull : s) * nn + 3 * s * nn + (Sc ? 32ull * ncp : 0ull);
       atomicAdd(a.counters + 4, bytes);
     }

@@ -42,9 +42,10 @@ struct InnerArgs {
   cplx<T>* V;                    // Krylov bases: solve s at V + s_offset*(maxit+1)
   cplx<T>* W;                    // packed work vector
   cplx<T>* X;                    // packed work vector
-  cplx<double>* R;               // per solve maxit*maxit upper-triangular factor
+  cplx<double>* R;               // per solve 2 maxit*maxit: the upper-triangular factor, then the
+                                 // upper-triangular coordinates T of the Krylov candidates
   cplx<double>* Sc;              // per solve (maxit + 2) coarse vectors of max_nc: E^{-1} Z^T f, E^{-1} Z^T B x0,
-                                 // E^{-1} Z^T B v_i (kept so that the recovery needs no coarse solve), or null
+                                 // E^{-1} Z^T B u~_i (kept so that the recovery needs no coarse solve), or null
   int* iters;                    // [nrhs][nsub] inner iterations, or null
   int* flags;                    // [nrhs][nsub] bit0 guess accepted, bit1 not converged
   const int* done;               // [nrhs] skip right-hand sides already converged, or null
