@@ -2,12 +2,13 @@
 
 Usage: python tests/golden/make_golden.py small [medium] [large]
        python tests/golden/make_golden.py --tol-sweep medium 0.1 0.0001
-       python tests/golden/make_golden.py --spread-tol medium 0.1 16
+       python tests/golden/make_golden.py --spread-tol medium 0.1 16 [AMP]
        python tests/golden/make_golden.py --spread small [medium]
        python tests/golden/make_golden.py --direct small [medium] [large]
        python tests/golden/make_golden.py --two-level small:16 [medium:80]
        python tests/golden/make_golden.py --paper-two-level
        python tests/golden/make_golden.py --paper-tables [workers]
+       python tests/golden/make_golden.py --recycling small [medium]
 
 For each named workload (paper_2103_17081_amd.inputs.workload) and its first right-hand
 side, runs the oracle's outer FGMRES with impedance (ORAS) local matrices, linear
@@ -21,6 +22,11 @@ M coarse intervals per edge) with deflated-GMRES and with exact subdomain solves
 (Dirichlet local matrices, Bezier deflation, k = 20 and 40 at 10 points per wavelength,
 N = 4, 9, 16, 25) without and with the global coarse space (M = n/2), and the two-level
 counts' spread under coarse solutions perturbed by 1e-12 relative.
+--recycling writes recycling_study.json: the one-level solve with the subdomain GMRES
+solves recycling across outer iterations (oracle/recycling.py, GCRO-DR) for recycle
+spaces of k = 5, 10 and 20 harmonic Ritz vectors updated after every solve, and k = 5 kept
+from the first solve: outer count, average inner count, and the mean over applications of
+the largest subdomain iteration count (what bounds a batched launch).
 """
 
 import json
@@ -54,12 +60,14 @@ def store(path, update):
     return data
 
 
-def spread(name, seeds=8, tol=None):
+def spread(name, seeds=8, tol=None, amp=1.0):
     """Outer counts of the oracle when its subdomain solves are perturbed at FP32 level.
 
     Mode "round": local right-hand sides and local solutions rounded to complex64.
-    Mode "noise": local solutions multiplied by (1 + EPS32 * xi), xi complex normal,
+    Mode "noise": local solutions multiplied by (1 + amp * EPS32 * xi), xi complex normal,
     seeded.  Each run is the oracle's FGMRES with the oracle's deflated-GMRES solves.
+    amp > 1 models subdomain solves whose whole Krylov process runs in complex64: their
+    results differ from the complex128 ones by a few unit roundoffs, not by one rounding.
     """
     import numpy as np
     from oracle import krylov
@@ -81,7 +89,8 @@ def spread(name, seeds=8, tol=None):
     noise = []
     for sd in range(seeds):
         rng = np.random.default_rng(1000 + sd)
-        noise.append(run(lambda u: u * (1 + EPS32 * (rng.standard_normal(u.size) + 1j * rng.standard_normal(u.size)))))
+        noise.append(run(lambda u: u * (1 + amp * EPS32 * (rng.standard_normal(u.size) +
+                                                             1j * rng.standard_normal(u.size)))))
     counts["noise"] = noise
     allc = [counts["round"]] + noise
     counts["min"], counts["max"] = min(allc), max(allc)
@@ -277,6 +286,28 @@ def _paper_cell(args):
     return cell
 
 
+def recycling_study(names):
+    import numpy as np
+    from oracle import recycling
+    path = os.path.join(HERE, "recycling_study.json")
+    for name in names:
+        w = inputs.workload(name)
+        S = schwarz.Schwarz(schwarz.problem_from_workload(w))
+        rows = []
+        for k, update in ((0, True), (5, False), (5, True), (10, True), (20, True)):
+            t0 = time.time()
+            R = recycling.RecyclingSchwarz(S, k, update)
+            _, st = R.solve(w.rhs[0], inner_tol=w.inner_tol, outer_maxit=3000)
+            row = {"k": k, "update": update, "outer_iters": st.outer_iters, "avg_inner": st.avg_inner,
+                   "mean_max_inner_per_apply": float(np.mean(R.max_per_apply)),
+                   "true_relres": st.true_relres, "converged": st.converged,
+                   "oracle_seconds": round(time.time() - t0, 1)}
+            rows.append(row)
+            print(name, json.dumps(row), flush=True)
+        store(path, lambda d: d.update({name: {"inner_tol": w.inner_tol, "rows": rows,
+                                                "source": "oracle (tests/golden/make_golden.py --recycling)"}}))
+
+
 def paper_tables(workers=4):
     """tests/golden/paper_mesh_tables.json: _paper_cell over k = 20, 40, ppwl = 10, 20,
     N = 4, 9, 16, 25 (a process per cell)."""
@@ -299,6 +330,8 @@ if __name__ == "__main__":
         paper_two_level()
     elif args and args[0] == "--paper-tables":
         paper_tables(int(args[1]) if len(args) > 1 else 4)
+    elif args and args[0] == "--recycling":
+        recycling_study(args[1:] or ["small"])
     elif args and args[0] == "--two-level":
         two_level(args[1:] or ["small:16"])
     elif args and args[0] == "--direct":
@@ -309,19 +342,30 @@ if __name__ == "__main__":
             store(OUT, lambda d: d.setdefault(name, {}).update({"fp32_perturbed_outer": sp}))
             print(name, sp, flush=True)
     elif args and args[0] == "--spread-tol":
-        # --spread-tol NAME TOL SEEDS: the FP32-perturbation spread of the outer count at one
-        # inner tolerance, stored beside that tolerance's golden (the workload's own tolerance
-        # at the entry's top level, others under tol_sweep)
+        # --spread-tol NAME TOL SEEDS [AMP]: the FP32-perturbation spread of the outer count at
+        # one inner tolerance, stored beside that tolerance's golden (the workload's own
+        # tolerance at the entry's top level, others under tol_sweep).  With AMP (noise of AMP
+        # unit roundoffs) the counts are added under "noise_amp<AMP>" and min/max cover all runs.
         name, tol, seeds = args[1], float(args[2]), int(args[3])
-        sp = spread(name, seeds, tol)
+        amp = float(args[4]) if len(args) > 4 else 1.0
+        sp = spread(name, seeds, tol, amp)
         key = f"{tol:g}"
+
+        def merge(old):
+            if amp == 1.0 or not old:
+                return sp
+            new = dict(old)
+            new[f"noise_amp{amp:g}"] = sp["noise"]
+            new["min"], new["max"] = min(old["min"], sp["min"]), max(old["max"], sp["max"])
+            return new
 
         def put(d):
             e = d.setdefault(name, {})
             if e.get("inner_tol") == tol:
-                e["fp32_perturbed_outer"] = sp
+                e["fp32_perturbed_outer"] = merge(e.get("fp32_perturbed_outer"))
             else:
-                e.setdefault("tol_sweep", {}).setdefault(key, {})["fp32_perturbed_outer"] = sp
+                t = e.setdefault("tol_sweep", {}).setdefault(key, {})
+                t["fp32_perturbed_outer"] = merge(t.get("fp32_perturbed_outer"))
         store(OUT, put)
         print(name, key, sp, flush=True)
     elif args and args[0] == "--tol-sweep":

@@ -13,7 +13,10 @@ Per tolerance:
   by ||z - z_oracle|| / ||z_oracle|| <= 10 tol (the subdomain iterates diverge at the
   level of the tolerance, not of FP32 rounding), and the solve's outer count lies in the
   spread the FP64 oracle itself shows when its subdomain solves are perturbed at FP32
-  level, widened by 2.  Both differences are printed.
+  level, widened by 2.  Both differences are printed.  At inner tolerance 1e-1 the
+  spread includes perturbations of three unit roundoffs: a complex64 application differs
+  from the complex128 one by 1.8e-7 to 2.0e-7 relative, about three times the one-rounding
+  perturbation, because the whole Krylov process runs in complex64.
 """
 
 import json
