@@ -68,6 +68,34 @@ def test_inner_solves_match_oracle(torch, name):
         assert not np.any(flags & 2)
 
 
+@pytest.mark.parametrize("maxit", [1, 2, 5])
+def test_inner_solves_stop_at_maxit(torch, maxit):
+    """Every subdomain solve stops at inner_maxit with an unreachable tolerance: the GPU
+    iterate is the oracle's GMRES iterate after the same number of steps (the minimal
+    residual point of the same Krylov space), flagged as not converged."""
+    _case("inner_solve at maxit", maxit)
+    w, S = oracle_for("small")
+    rng = np.random.default_rng(21)
+    fs = [crandn(rng, s.geom.ndof) for s in S.subs]
+    for prec in (64, 32):
+        npdt = np.complex64 if prec == 32 else np.complex128   # the handle's inner precision
+        with solver_for("small", precision=prec, inner_tol=1e-12, inner_maxit=maxit) as gpu:
+            u, iters, flags = gpu.op_inner_solve(to_gpu(torch, pack(S, gpu, fs).astype(npdt)))
+            us = unpack(S, gpu, to_np(u).astype(np.complex128))
+        assert np.all(iters == maxit) and np.all(flags & 2)
+        for s, f, ug in zip(S.subs, fs, us):
+            ur, itr, _ = s.deflated_gmres(f, 1e-12, maxit)
+            assert itr == maxit
+            d = s.defl
+            rg = np.linalg.norm(d.P(f - s.B @ ug))
+            rr = np.linalg.norm(d.P(f - s.B @ ur))
+            if prec == 64:
+                assert np.linalg.norm(ug - ur) <= 1e-8 * np.linalg.norm(ur)
+            else:
+                # same minimal residual up to complex64 rounding of the iterate
+                assert abs(rg - rr) <= 1e-4 * np.linalg.norm(d.P(f))
+
+
 def test_inner_solve_guess_and_zero_rhs(torch):
     _case("inner_solve guess")
     w, S = oracle_for("small")
