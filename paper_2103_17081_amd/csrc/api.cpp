@@ -104,7 +104,7 @@ struct dd_handle {
   // outer FGMRES
   cplx<double>* Vo = nullptr;   // [nrhs][restart + 1][ndof]
   cplx<double>* Zo = nullptr;   // [nrhs][restart][ndof]
-  cplx<double>* part = nullptr; // [nrhs][pstride][chunks]
+  cplx<double>* part = nullptr; // [nrhs][pstride][chunks] (launch_dots), [nrhs][chunks][pstride] + segments (dots2)
   cplx<double>* coef = nullptr; // [nrhs][pstride]
   cplx<double>* ca = nullptr;   // [nrhs][restart] delayed-CGS2 update coefficients
   cplx<double>* cb = nullptr;
@@ -574,7 +574,9 @@ dd_status dd_setup(const dd_params* p, void* stream, dd_handle** out) {
     DD_TRY(h->alloc(&h->Vo, (size_t)h->nrhs * (m + 1) * h->ndof));
     DD_TRY(h->alloc(&h->Zo, (size_t)h->nrhs * m * h->ndof));
     h->pstride = 2 * m + 4;
-    DD_TRY(h->alloc(&h->part, (size_t)h->nrhs * ddh::outer_chunks(h->ndof) * h->pstride));
+    DD_TRY(h->alloc(&h->part, (size_t)h->nrhs * h->pstride *
+                                  std::max<size_t>(ddh::outer_chunks(h->ndof),
+                                                   ddh::dots2_chunks(h->ndof) + ddh::dots2_segments(h->ndof))));
     DD_TRY(h->alloc(&h->coef, (size_t)h->nrhs * h->pstride));
     DD_TRY(h->alloc(&h->ca, (size_t)h->nrhs * m));
     DD_TRY(h->alloc(&h->cb, (size_t)h->nrhs * m));
@@ -738,8 +740,7 @@ static dd_status enqueue_outer_step(dd_handle* h, int slot, hipStream_t st, bool
   DD_HIP(ddh::launch_dots2(h->Vo, vstr, nullptr, 0, nullptr, 0, nd, sr, 1, m, h->part, h->pstride, nr, o.done, st,
                            h->dots_blocks));
   DD_TRY(mark(5));
-  DD_HIP(ddh::launch_reduce_parts(h->part, ddh::dots2_chunks(nd), h->pstride, sr, 2, 3, m, h->coef, h->pstride,
-                                  nullptr, 0, 2, nr, o.done, st));
+  DD_HIP(ddh::launch_reduce_chunks(h->part, nd, h->pstride, sr, 2, 3, m, h->coef, h->pstride, nr, o.done, st));
   DD_HIP(ddh::launch_dcgs2_step(o, sr, m, nd, h->coef, h->pstride, 1, h->ca, h->cb, m, h->scal, nr, st));
   DD_TRY(mark(6));
   DD_HIP(ddh::launch_dcgs2_update(h->Vo, vstr, nd, sr, h->ca, h->cb, m, h->scal, nr, o.done, st));
@@ -848,8 +849,8 @@ dd_status dd_solve(dd_handle* h, const void* fv, void* uv, void* stream, dd_stat
       // end of a cycle: finalise column m-1 from v~_m alone
       DD_HIP(ddh::launch_dots2(h->Vo, vstr, h->Vo + (long long)m * nd, vstr, nullptr, 0, nd, ddh::host_step(m), 0, m,
                                h->part, h->pstride, nr, o.done, st, h->dots_blocks));
-      DD_HIP(ddh::launch_reduce_parts(h->part, ddh::dots2_chunks(nd), h->pstride, ddh::host_step(m), 2, 3, m,
-                                      h->coef, h->pstride, nullptr, 0, 2, nr, o.done, st));
+      DD_HIP(ddh::launch_reduce_chunks(h->part, nd, h->pstride, ddh::host_step(m), 2, 3, m, h->coef, h->pstride, nr,
+                                       o.done, st));
       DD_HIP(ddh::launch_dcgs2_step(o, ddh::host_step(m), m, nd, h->coef, h->pstride, 0, h->ca, h->cb, m, h->scal,
                                     nr, st));
       DD_TRY(sync_done());

@@ -48,6 +48,8 @@ hipError_t launch_residual(const cplx<double>* f, long long fstride, cplx<double
                            long long ndof, int nblk, int nrhs, hipStream_t st);
 int outer_chunks(long long ndof);   // row chunks of the dots / update sweeps (part layout of launch_dots)
 __host__ __device__ int dots2_chunks(long long ndof);   // row chunks of launch_dots2 (its part layout)
+// segments of launch_reduce_chunks: part must hold nrhs * (dots2_chunks + dots2_segments) * pstride values
+__host__ __device__ int dots2_segments(long long ndof);
 hipError_t configure_outer();
 hipError_t launch_fill_hash(cplx<double>* x, long long n, unsigned long long seed, hipStream_t st);   // dynamic-LDS limits of the bookkeeping kernels, at set-up
 hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<double>* w, long long wstride,
@@ -63,6 +65,10 @@ hipError_t launch_update(const cplx<double>* basis, long long bstride, cplx<doub
 hipError_t launch_scale(const cplx<double>* w, long long wstride, cplx<double>* out, long long ostride,
                         long long ndof, const double* scale, int nblk, int nrhs, const int* done,
                         hipStream_t st);
+// out[rhs][s] = sum over launch_dots2's chunks, s < mul * j + add (j from sr; jmax sizes the grid);
+// the segment sums are kept in part after the chunk partials
+hipError_t launch_reduce_chunks(const cplx<double>* part, long long ndof, int pstride, StepRef sr, int mul, int add,
+                                int jmax, cplx<double>* out, int ostride, int nrhs, const int* done, hipStream_t st);
 hipError_t launch_dots2(const cplx<double>* basis, long long bstride, const cplx<double>* x1, long long x1stride,
                         const cplx<double>* x2, long long x2stride, long long ndof, StepRef sr, int two, int jmax,
                         cplx<double>* part, int pstride, int nrhs, const int* done, hipStream_t st,

@@ -145,9 +145,12 @@ __global__ void __launch_bounds__(256) dots_kernel(const cplx<double>* __restric
 // nvec grows.  All loads of an item are issued before the products are formed, and
 // each thread covers kD2Rows rows so the per-item reduction (DPP sums over 16-lane
 // rows, then one LDS pass over the 16 row partials of the workgroup) is amortised over
-// 128 KB of basis.  With `sr.jdev` set, nvec = *jdev and x1, x2 are basis vectors nvec
+// 128 KB of basis; the LDS partials alternate between two buffers, so an item needs one
+// LDS-only barrier.  With `sr.jdev` set, nvec = *jdev and x1, x2 are basis vectors nvec
 // and nvec+1 (graph-captured steps); otherwise nvec = sr.jhost and x1, x2 are the given
-// vectors.  part layout: [rhs][slot][chunk], dots2_chunks(ndof) chunks.
+// vectors.  part layout: [rhs][chunk][slot] (pstride slots per chunk), dots2_chunks(ndof)
+// chunks: an item's partials land in two or three contiguous runs (partials scattered
+// one per slot row, 16 bytes apart by a chunk count, cost the sweep 8% of its time).
 constexpr int kD2Rows = 8;
 constexpr int kD2Vecs = 4;
 constexpr int kD2Chunk = kD2Rows * 256;
@@ -163,10 +166,11 @@ __global__ void __launch_bounds__(256) dots2_kernel(const cplx<double>* __restri
                                                     const int* __restrict__ done) {
   const int rhs = blockIdx.z;
   if (done && done[rhs]) return;
-  __shared__ double red[16][kD2Vals];
+  __shared__ double red[2][16][kD2Vals];
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const int rowgrp = wave * 4 + lane / 16, li = lane % 16;
   const int nvec = sr.get();
+  int buf = 0;
   const bool two = two_in != 0;
   const cplx<double>* X1 = sr.jdev ? basis + rhs * bstride + (long long)nvec * ndof : x1 + rhs * x1stride;
   const cplx<double>* X2 = sr.jdev ? basis + rhs * bstride + (long long)(nvec + 1) * ndof
@@ -236,9 +240,11 @@ __global__ void __launch_bounds__(256) dots2_kernel(const cplx<double>* __restri
 #pragma unroll
     for (int e = 0; e < kD2Vals; ++e) {
       const double t = row_sum<16>(pv[e]);
-      if (li == 0) red[rowgrp][e] = t;
+      if (li == 0) red[buf][rowgrp][e] = t;
     }
-    __syncthreads();
+    // the readers below finish with red[buf] before this item's successor passes its own
+    // barrier, so the item after that may overwrite it
+    lds_barrier();
     if (tid < 2 * kD2Vecs + 3) {
       int slot = -1;
       if (tid < kD2Vecs) slot = tid < cnt ? s0 + tid : -1;
@@ -247,12 +253,53 @@ __global__ void __launch_bounds__(256) dots2_kernel(const cplx<double>* __restri
       if (slot >= 0) {
         cplx<double> t = czero<double>();
 #pragma unroll
-        for (int g = 0; g < 16; ++g) t = t + cplx<double>{red[g][2 * tid], red[g][2 * tid + 1]};
-        part[((long long)rhs * pstride + slot) * nchunk + chunk] = t;
+        for (int g = 0; g < 16; ++g) t = t + cplx<double>{red[buf][g][2 * tid], red[buf][g][2 * tid + 1]};
+        part[((long long)rhs * nchunk + chunk) * pstride + slot] = t;
       }
     }
-    __syncthreads();
+    buf ^= 1;
   }
+}
+
+// Sum of launch_dots2's partials over the row chunks, in two fixed-order stages so that
+// the result does not depend on scheduling: stage 1 sums segments of kSegChunks chunks
+// (seg[rhs][segment][slot]), stage 2 sums the segments into out[rhs][slot] for
+// slot < mul * j + add.  Consecutive threads take consecutive slots (coalesced rows).
+constexpr int kSegChunks = 8;
+__host__ __device__ int dots2_segments(long long ndof) { return (dots2_chunks(ndof) + kSegChunks - 1) / kSegChunks; }
+
+__global__ void __launch_bounds__(256) reduce_chunks_kernel(const cplx<double>* __restrict__ part, int nchunk,
+                                                            int pstride, StepRef sr, int mul, int add,
+                                                            cplx<double>* __restrict__ seg,
+                                                            const int* __restrict__ done) {
+  const int rhs = blockIdx.z;
+  if (done && done[rhs]) return;
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= mul * sr.get() + add) return;
+  const int nseg = (nchunk + kSegChunks - 1) / kSegChunks;
+  const int c0 = blockIdx.y * kSegChunks, c1 = min(nchunk, c0 + kSegChunks);
+  const cplx<double>* p = part + (long long)rhs * nchunk * pstride + s;
+  cplx<double> v[kSegChunks];
+#pragma unroll
+  for (int q = 0; q < kSegChunks; ++q) v[q] = c0 + q < c1 ? p[(long long)(c0 + q) * pstride] : czero<double>();
+  cplx<double> acc = czero<double>();
+#pragma unroll
+  for (int q = 0; q < kSegChunks; ++q) acc = acc + v[q];
+  seg[((long long)rhs * nseg + blockIdx.y) * pstride + s] = acc;
+}
+
+__global__ void __launch_bounds__(256) reduce_segments_kernel(const cplx<double>* __restrict__ seg, int nseg,
+                                                              int pstride, StepRef sr, int mul, int add,
+                                                              cplx<double>* __restrict__ out, int ostride,
+                                                              const int* __restrict__ done) {
+  const int rhs = blockIdx.z;
+  if (done && done[rhs]) return;
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= mul * sr.get() + add) return;
+  const cplx<double>* p = seg + (long long)rhs * nseg * pstride + s;
+  cplx<double> acc = czero<double>();
+  for (int g = 0; g < nseg; ++g) acc = acc + p[(long long)g * pstride];
+  out[(long long)rhs * ostride + s] = acc;
 }
 
 // Stage 2: out[rhs][s] = sum over chunks for s < nslots = mul * j + add (j from the
@@ -717,6 +764,19 @@ hipError_t launch_scale(const cplx<double>* w, long long wstride, cplx<double>* 
                         hipStream_t st) {
   hipLaunchKernelGGL(scale_kernel, dim3(nblk, nrhs), dim3(256), 0, st, w, wstride, out, ostride, ndof, scale,
                      done);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_chunks(const cplx<double>* part, long long ndof, int pstride, StepRef sr, int mul, int add,
+                                int jmax, cplx<double>* out, int ostride, int nrhs, const int* done, hipStream_t st) {
+  const int nchunk = dots2_chunks(ndof), nseg = dots2_segments(ndof);
+  const int sblocks = (mul * jmax + add + 255) / 256;
+  // the segment sums go after the partials of every right-hand side
+  cplx<double>* seg = const_cast<cplx<double>*>(part) + (long long)nrhs * nchunk * pstride;
+  hipLaunchKernelGGL(reduce_chunks_kernel, dim3(sblocks, nseg, nrhs), dim3(256), 0, st, part, nchunk, pstride, sr,
+                     mul, add, seg, done);
+  hipLaunchKernelGGL(reduce_segments_kernel, dim3(sblocks, 1, nrhs), dim3(256), 0, st, (const cplx<double>*)seg, nseg,
+                     pstride, sr, mul, add, out, ostride, done);
   return hipGetLastError();
 }
 
