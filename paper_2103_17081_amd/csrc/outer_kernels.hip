@@ -298,7 +298,14 @@ __global__ void __launch_bounds__(256) reduce_segments_kernel(const cplx<double>
   if (s >= mul * sr.get() + add) return;
   const cplx<double>* p = seg + (long long)rhs * nseg * pstride + s;
   cplx<double> acc = czero<double>();
-  for (int g = 0; g < nseg; ++g) acc = acc + p[(long long)g * pstride];
+  for (int g0 = 0; g0 < nseg; g0 += kSegChunks) {
+    // a batch of independent loads, then the sums in segment order
+    cplx<double> v[kSegChunks];
+#pragma unroll
+    for (int q = 0; q < kSegChunks; ++q) v[q] = g0 + q < nseg ? p[(long long)(g0 + q) * pstride] : czero<double>();
+#pragma unroll
+    for (int q = 0; q < kSegChunks; ++q) acc = acc + v[q];
+  }
   out[(long long)rhs * ostride + s] = acc;
 }
 
