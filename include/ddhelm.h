@@ -237,8 +237,9 @@ dd_status dd_op_inner_solve(dd_handle* h, const void* f, const void* guess, void
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
    serving loops, harnesses that forbid hipMalloc): dd_op_inner_solve without a guess, with
-   every scratch buffer of the subdomain solves -- Krylov bases, R factors, kept coarse
-   vectors, work tiles, per-solve counts and flags, counters -- taken from a static device
+   every scratch buffer of the subdomain solves -- Krylov bases, R factors and candidate
+   coordinates, kept coarse vectors, work tiles, per-solve counts and flags, counters --
+   taken from a static device
    array of 64 MiB that each GPU holds from library load until the process ends, instead of
    the handle's workspaces.  Calls nothing that allocates.  f (packed [nrhs][nfine], the
    handle's inner precision) is read in place and must not change until the solves are done;
