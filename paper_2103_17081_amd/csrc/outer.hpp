@@ -55,7 +55,7 @@ hipError_t launch_fill_hash(cplx<double>* x, long long n, unsigned long long see
 hipError_t launch_dots(const cplx<double>* basis, long long bstride, const cplx<double>* w, long long wstride,
                        long long ndof, int nvec, int with_norm, cplx<double>* part, int pstride, int nrhs,
                        const int* done, hipStream_t st);
-// nchunk: the chunk count of the producing sweep (outer_chunks or dots2_chunks)
+// sums launch_dots' partials ([rhs][slot][chunk], nchunk = outer_chunks(ndof)) over the chunks
 hipError_t launch_reduce_parts(const cplx<double>* part, int nchunk, int pstride, StepRef sr, int mul, int add,
                                int jmax, cplx<double>* out, int ostride, cplx<double>* H, int hstride, int mode,
                                int nrhs, const int* done, hipStream_t st);
