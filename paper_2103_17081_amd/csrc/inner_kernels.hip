@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(NT) inner_solve_kernel(InnerArgs<T> a) {
   if (a.done && a.done[rhs]) return;
   const SubDesc d = a.subs[sub];
   Lds<T> L = carve<T, NT>(smem, a.max_nj, a.max_nc, a.maxit);
-  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int tid = threadIdx.x;
   const int nx = d.nx, nj = d.nx * d.ny;
   const int maxit = a.maxit;
   const long long fo = (long long)rhs * a.nfine + d.off;
