@@ -119,21 +119,25 @@ constexpr int kDppXor2 = 0x4E;          // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;   // row_half_mirror
 constexpr int kDppMirror = 0x140;       // row_mirror
 
-template <int Ctrl>
+constexpr int kDppBcast15 = 0x142;      // row_bcast:15 (last lane of each row to the next row)
+constexpr int kDppBcast31 = 0x143;      // row_bcast:31 (lane 31 to rows 2 and 3)
+
+// DPP move of v; rows outside RowMask read 0.
+template <int Ctrl, int RowMask = 0xF>
 __device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, RowMask, 0xF, false));
 }
-template <int Ctrl>
+template <int Ctrl, int RowMask = 0xF>
 __device__ __forceinline__ double dpp_f64(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), Ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), Ctrl, RowMask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, RowMask, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <int Ctrl>
-__device__ __forceinline__ float dpp(float v) { return dpp_f32<Ctrl>(v); }
-template <int Ctrl>
-__device__ __forceinline__ double dpp(double v) { return dpp_f64<Ctrl>(v); }
+template <int Ctrl, int RowMask = 0xF>
+__device__ __forceinline__ float dpp(float v) { return dpp_f32<Ctrl, RowMask>(v); }
+template <int Ctrl, int RowMask = 0xF>
+__device__ __forceinline__ double dpp(double v) { return dpp_f64<Ctrl, RowMask>(v); }
 
 // Sum over each aligned group of `Lanes` (2, 4, 8 or 16) lanes; all lanes get it.
 template <int Lanes, typename T>
@@ -146,6 +150,18 @@ __device__ __forceinline__ T row_sum(T v) {
   return v;
 }
 
+// Sum over the whole wavefront, valid in its last lane only: the 16-lane row sums, then
+// row 1 (3) adds the last lane of row 0 (2), then rows 2 and 3 add lane 31.  VALU only:
+// no LDS crossbar traffic, unlike the shuffle butterfly of wave_sum.
+template <typename T>
+__device__ __forceinline__ T wave_total(T v) {
+  v = row_sum<16>(v);
+  v += dpp<kDppBcast15, 0xA>(v);
+  v += dpp<kDppBcast31, 0xC>(v);
+  return v;
+}
+
+// Sum over the whole wavefront; every lane gets it.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -249,10 +249,10 @@ __device__ __forceinline__ void deflated_op(const SubDesc& d, const cplx<double>
 // Workgroup sum of a real partial; every thread gets the total.
 template <typename T, int NT>
 __device__ __forceinline__ double block_sum(T part, Lds<T>& L) {
-  part = wave_sum(part);
+  part = wave_total(part);
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   lds_barrier();
-  if (lane == 0) L.red[wave].re = part;
+  if (lane == kWave - 1) L.red[wave].re = part;
   lds_barrier();
   double s = 0.0;
 #pragma unroll
@@ -263,10 +263,10 @@ __device__ __forceinline__ double block_sum(T part, Lds<T>& L) {
 
 template <int NT>
 __device__ __forceinline__ double block_sum_f64(double part, double* red) {
-  part = wave_sum(part);
+  part = wave_total(part);
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   lds_barrier();
-  if (lane == 0) red[wave] = part;
+  if (lane == kWave - 1) red[wave] = part;
   lds_barrier();
   double s = 0.0;
 #pragma unroll
@@ -324,17 +324,17 @@ __device__ __forceinline__ void basis_dots(const cplx<T>* __restrict__ V, int nj
     for (int q = 0; q < kDotChunk; ++q) {
       if (i0 + q <= k) {
         cplx<T> p = acc[q];
-        p.re = wave_sum(p.re);
-        p.im = wave_sum(p.im);
-        if (lane == 0) red[wave * S + i0 + q] = p;
+        p.re = wave_total(p.re);
+        p.im = wave_total(p.im);
+        if (lane == kWave - 1) red[wave * S + i0 + q] = p;
       }
     }
   }
   if (with_norm) {
     T q = T(0);
     for (int n = tid; n < nj; n += NT) q += cabs2(B[n]);
-    q = wave_sum(q);
-    if (lane == 0) red[wave * S + k + 1] = cplx<T>{q, T(0)};
+    q = wave_total(q);
+    if (lane == kWave - 1) red[wave * S + k + 1] = cplx<T>{q, T(0)};
   }
 }
 
