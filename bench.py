@@ -33,7 +33,9 @@ headline workload's chosen form at inner tolerances 1e-3 and 1e-4; `restart_stud
 one-level chosen form with restarted FGMRES (restart 100, 300, 1000, 2000); `xlarge` solves the
 largest one-GPU configuration (k = 400, N = 1274, 32 x 32 perturbed blocks, eight
 right-hand sides) with the two-level method as two unrestarted batches of four, in the
-chosen, complex128 and exact-local-solve forms.  `--xlarge-batches` runs only that leg.
+chosen, complex128 and exact-local-solve forms.  `--xlarge-batches` runs only that leg, and
+`--breakeven` only a study of the one-level method over uniform P x P partitions of the
+headline grid (P = 12 ... 32), inexact against exact subdomain solves.
 Progress goes to stderr; stdout carries the one result line.
 """
 
@@ -111,6 +113,9 @@ def parse():
                     help="skip the restarted-FGMRES study (restart 100, 300, 1000, 2000) of the one-level solve")
     ap.add_argument("--no-xlarge", action="store_true",
                     help="skip the k = 400 eight-right-hand-side leg (two-level, batches of four)")
+    ap.add_argument("--breakeven", action="store_true",
+                    help="only: the one-level method on the k = 200 grid over uniform P x P partitions, inexact "
+                         "(chosen form) against exact subdomain solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-outer", type=int, default=40, help="outer iterations of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -334,6 +339,50 @@ def restart_leg(torch, w, f, restarts=(100, 300, 1000, 2000), maxit=6000):
     return rows
 
 
+def apply_ms(torch, solver, j: int, reps: int = 5) -> float:
+    """Median duration (HIP events on torch's stream) of one preconditioner application to
+    outer basis vector j of the solver's last solve."""
+    r = solver.outer_basis(j).contiguous()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        solver.apply_preconditioner(r)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return sorted(ts)[len(ts) // 2]
+
+
+def breakeven_leg(torch, w, f, parts=(12, 16, 20, 24, 32), maxit=4000):
+    """The one-level method on the headline grid over uniform P x P partitions, inexact
+    subdomain solves (chosen form) against exact ones: time to solution and time per
+    preconditioner application as the subdomains shrink, i.e. where the inexact solves
+    start to pay (the wall-clock question the paper leaves open, Sec. 4)."""
+    import dataclasses
+    from paper_2103_17081_amd import inputs
+    rows = []
+    for P in parts:
+        cuts = inputs.uniform_cuts(w.n, P)
+        wp = dataclasses.replace(w, cuts_x=cuts, cuts_y=cuts)
+        row = {"subdomains": f"{P}x{P}", "widest_block_cells": int(max(cuts[1:] - cuts[:-1]))}
+        for form, prec, local in (("inexact_c64", 32, "deflated"), ("exact", 64, "direct")):
+            progress(f"break-even {P}x{P} {form}")
+            s = make_solver(wp, prec, local, outer_maxit=maxit)
+            s.autotune(None)
+            t, u, st = timed_solves(torch, s, f, 1, 1)
+            last = st[-1]
+            entry = {"time_to_solution_s": t, "outer_iters": last["outer_iters"], "status": last["status"],
+                     "true_relres": true_relres(torch, s, f, u),
+                     "ms_per_apply_basis_300": apply_ms(torch, s, min(300, last["outer_iters"] - 1))}
+            if local == "deflated":
+                entry["avg_inner_iters"] = last["inner_iters_total"] / max(last["subdomain_solves"], 1)
+            row[form] = entry
+            s.close()
+        rows.append(row)
+    return rows
+
+
 def two_level_leg(torch, w, f, M: int, t_one_level=None, direct: bool = True):
     """The two-level method (global coarse space of M intervals per edge) in the chosen
     form, and with exact subdomain solves; t_one_level (s) gives the speedups."""
@@ -377,8 +426,8 @@ def two_level_leg(torch, w, f, M: int, t_one_level=None, direct: bool = True):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); multi-GPU runs are not part of "
-              "this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the solver has no multi-GPU path",
+              file=sys.stderr)
         return 2
     import torch
     from paper_2103_17081_amd import inputs
@@ -394,6 +443,9 @@ def main():
         del src, dst
     if args.xlarge_batches:
         print(json.dumps({"xlarge_batches": xlarge_batches(torch)}), flush=True)
+        return 0
+    if args.breakeven:
+        print(json.dumps({"breakeven": breakeven_leg(torch, w, f)}), flush=True)
         return 0
     if args.two_level_only:
         M = args.coarse_intervals or default_coarse_intervals(w)

@@ -943,26 +943,22 @@ hipError_t launch_scatter(const SubDesc* subs, int nsub, Consts cs, const cplx<T
 
 template <typename T>
 hipError_t configure_inner(int max_nj, int max_nc, int maxit) {
-  const size_t lds = lds_bytes<T>(max_nj, max_nc, maxit, kInnerThreads);
-  hipError_t e = hipSuccess;
-  if (lds > 65536)
-    e = hipFuncSetAttribute((const void*)inner_solve_kernel<T, kInnerThreads>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  const size_t lds256 = lds_bytes<T>(max_nj, max_nc, maxit, 256);
-  if (e == hipSuccess && lds256 > 65536)
-    e = hipFuncSetAttribute((const void*)inner_solve_kernel<T, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds256);
-  const size_t lds2 = lds_bytes<T>(max_nj, max_nc, 1, kBlock);
-  if (e == hipSuccess && lds2 > 65536)
-    e = hipFuncSetAttribute((const void*)deflated_apply_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds2);
-  const size_t lds3 = align16(kClasses * kStencilPts * sizeof(cplx<T>)) + (size_t)max_nj * sizeof(cplx<T>);
-  if (e == hipSuccess && lds3 > 65536)
-    e = hipFuncSetAttribute((const void*)local_apply_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds3);
-  const size_t lds4 = 5 * (size_t)max_nc * sizeof(cplx<double>);
-  if (e == hipSuccess && lds4 > 65536)
-    e = hipFuncSetAttribute((const void*)coarse_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds4);
+  int dev = 0, maxlds = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  // A kernel whose LDS at these sizes exceeds the device limit is left unconfigured: set-up
+  // has already rejected the handle unless it never launches that kernel (exact local solves
+  // do not run the subdomain GMRES), and a launch of it is refused by the runtime.
+  auto set = [&](const void* fn, size_t lds) {
+    if (e == hipSuccess && lds > 65536 && lds <= (size_t)maxlds)
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  };
+  set((const void*)inner_solve_kernel<T, kInnerThreads>, lds_bytes<T>(max_nj, max_nc, maxit, kInnerThreads));
+  set((const void*)inner_solve_kernel<T, 256>, lds_bytes<T>(max_nj, max_nc, maxit, 256));
+  set((const void*)deflated_apply_kernel<T>, lds_bytes<T>(max_nj, max_nc, 1, kBlock));
+  set((const void*)local_apply_kernel<T>,
+      align16(kClasses * kStencilPts * sizeof(cplx<T>)) + (size_t)max_nj * sizeof(cplx<T>));
+  set((const void*)coarse_solve_kernel, 5 * (size_t)max_nc * sizeof(cplx<double>));
   return e;
 }
 

@@ -81,3 +81,34 @@ def test_direct_solve_counts(torch, name):
             assert st["status"] == "DD_OK" and rel <= 1e-6
             assert abs(st["outer_iters"] - gold["outer_iters"]) <= 1
             assert st["inner_iters_total"] == 0 and st["subdomain_solves"] == st["precond_applies"] * len(S.subs)
+
+
+def test_direct_on_tiles_too_wide_for_the_subdomain_gmres(torch):
+    """The large grid cut 12 x 12 (tiles of 55 x 55 nodes): the complex128 subdomain GMRES
+    needs more LDS than a workgroup has, so a handle with it is refused at set-up
+    (DD_EINVAL, not a HIP error), while a handle with exact local solves, which never runs
+    that kernel, sets up and solves sampled subdomains like the oracle's sparse LU."""
+    import dataclasses
+
+    from oracle import schwarz
+    from paper_2103_17081_amd import inputs
+    from paper_2103_17081_amd.binding import DD_EINVAL, DDError, Solver
+
+    _case("direct local solves, large grid 12x12")
+    w = inputs.workload("large")
+    cuts = inputs.uniform_cuts(w.n, 12)
+    w = dataclasses.replace(w, cuts_x=cuts, cuts_y=cuts)
+    kw = dict(n_intervals=w.n, cuts_x=cuts, cuts_y=cuts, overlap=w.overlap, inner_precision=64, outer_maxit=10)
+    with pytest.raises(DDError) as err:
+        Solver(w.k, **kw)
+    assert err.value.status == DD_EINVAL and "LDS" in str(err.value)
+    S = schwarz.Schwarz(schwarz.problem_from_workload(w))
+    with Solver(w.k, local_solver="direct", **kw) as gpu:
+        rng = np.random.default_rng(43)
+        fs = [crandn(rng, s.geom.ndof) for s in S.subs]
+        u, iters, flags = gpu.op_inner_solve(to_gpu(torch, pack(S, gpu, fs)))
+        us = unpack(S, gpu, to_np(u))
+        assert not iters.any() and not flags.any()
+        for j in rng.choice(len(S.subs), 6, replace=False):
+            ref = S.subs[j].direct(fs[j])
+            assert np.linalg.norm(us[j] - ref) <= 1e-10 * np.linalg.norm(ref), j
