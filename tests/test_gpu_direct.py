@@ -84,8 +84,8 @@ def test_direct_solve_counts(torch, name):
 
 
 def test_direct_on_tiles_too_wide_for_the_subdomain_gmres(torch):
-    """The large grid cut 12 x 12 (tiles of 55 x 55 nodes): the complex128 subdomain GMRES
-    needs more LDS than a workgroup has, so a handle with it is refused at set-up
+    """The large grid cut 12 x 12 (tiles up to 56 x 56 nodes): the complex128 subdomain GMRES
+    needs more LDS than a workgroup has (189 KB), so a handle with it is refused at set-up
     (DD_EINVAL, not a HIP error), while a handle with exact local solves, which never runs
     that kernel, sets up and solves sampled subdomains like the oracle's sparse LU."""
     import dataclasses
