@@ -242,7 +242,7 @@ def _paper_cell(args):
     """One (k, ppwl, N) cell of the paper's Tables 1-4 in its own setting (Dirichlet local
     matrices, Bezier deflation, n_glob interior nodes per edge, point source at the centre):
     outer counts and average inner counts with direct subdomain solves and with deflated
-    GMRES at inner tolerances 1e-10, 1e-5 and 1e-2; plus the survey's A5 diagnostic, the
+    GMRES at inner tolerances 1e-10, 1e-5 and 1e-2; plus the no-recovery diagnostic, the
     1e-10 run with the local solution taken as the deflated system's x (no recovery)."""
     import numpy as np
     from oracle import krylov
@@ -260,7 +260,7 @@ def _paper_cell(args):
     for tol in (1e-10, 1e-5, 1e-2):
         _, st = S.solve(f, mode="deflated", inner_tol=tol, inner_maxit=300, outer_maxit=3000)
         cell[f"{tol:g}"] = {"outer": st.outer_iters, "avg_inner": st.avg_inner, "relres": st.true_relres}
-    # A5: no recovery -- the subdomain "solution" is x of P B x = P f
+    # no recovery: the subdomain "solution" is x of P B x = P f
     stats = schwarz.SolveStats()
 
     def apply_x(r):

@@ -14,8 +14,8 @@ tables is not asserted ("parity unpinned").  Asserted instead:
   (1e-2 >= direct - 2);
 * exact inner solves reproduce the direct counts: the 1e-10 runs are within 3 of Table 1's
   analogue (with the recovery step the inner tolerance bounds the true local residual);
-* the survey's A5 diagnostic: taking the deflated system's x as the local solution (no
-  recovery) does not reproduce the paper's modest 1e-10 excess over its direct counts --
+* the no-recovery diagnostic: taking the deflated system's x as the local solution (no
+  recovery step) does not reproduce the paper's modest 1e-10 excess over its direct counts --
   FGMRES needs over ten times the iterations or does not converge in 3000;
 * the oracle's direct counts lie within [0.7, 1.5] times the paper's Table 1 values, cell
   by cell (a band, stated here, not a parity claim);
