@@ -321,7 +321,7 @@ void dd_net_default_params(dd_net_params* p);
    field, has widths the network does not support, a parameter count that differs from
    what its widths need or from the bytes that follow, or a non-finite parameter; then as
    dd_net_create (DD_EINVAL for tile / max_batch, DD_ENOMEM, DD_EHIP).  The weights of the
-   guess network are this build's (the paper has no learned part). */
+   guess network are this library's own (the paper has no learned part). */
 dd_status dd_net_load(const char* path, int tile, int max_batch, dd_net** out);
 /* Allocate a network and its device workspaces.  DD_EINVAL for unsupported sizes. */
 dd_status dd_net_create(const dd_net_params* p, dd_net** out);

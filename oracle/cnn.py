@@ -1,7 +1,7 @@
 """float64 reference of the learned initial-guess network (oracle; test infrastructure only).
 
 The paper has no learned component; the subdomain solver it describes starts GMRES
-from a zero guess (Sec. 3).  The build adds an optional initial guess produced by a
+from a zero guess (Sec. 3).  This library adds an optional initial guess produced by a
 small convolutional encoder-decoder from the subdomain right-hand side; the guess is
 used only if it lowers the deflated residual, so the method itself is unchanged.
 

@@ -5,8 +5,8 @@ and LDS: compiled for gfx950 with the library's own flags, neither of its instan
 Why this is a test: a spill inside the coarse solve's step loop is reloaded through a wait on
 every factor load in flight, which made the complex64 kernel 7% slower on the large workload,
 and the kernel sits at the 256-register limit, so an edit anywhere in it can push the register
-allocator over that edge.  The check reads the code-object metadata of this build's own
-assembly (private segment size and VGPR spill count per kernel).  The complex128 kernels are
+allocator over that edge.  The check reads the code-object metadata of the assembly that
+hipcc produces here (private segment size and VGPR spill count per kernel).  The complex128 kernels are
 not held to it: at 512 threads they spill two registers, and a shorter factor ring that removes
 the spills measured no faster over whole solves.
 """
